@@ -1,0 +1,161 @@
+/*
+ * ebbkc.h -- exact k-clique counting and listing on one MI355X (gfx950).
+ *
+ * The method is EBBkC (Wang, Yu, Long, "Efficient k-Clique Listing: An
+ * Edge-Oriented Branching Strategy", SIGMOD 2024) in its hybrid form
+ * EBBkC-H with early termination (Section 4.4 and Section 5):
+ *
+ *   1. ebbkc_prepare computes the truss-based edge ordering pi_tau of the
+ *      input graph (Section 4.2, Eq. truss-based-edge), taken
+ *      level-synchronously: at level s every remaining edge with at most s
+ *      common neighbours in the remaining graph is removed in one round and
+ *      ranked by (round, edge id).  level(e) is the s at which e is removed
+ *      and tau is the largest level (Eq. tau bounds every sub-branch size by
+ *      it).  The ranks are stored next to the adjacency.
+ *   2. ebbkc_count / ebbkc_list branch on every edge e_i = (u,v) in that
+ *      order (Eq. edge-oriented-branching): the sub-branch graph g_i has the
+ *      common neighbours of u and v through edges ranked after e_i, and the
+ *      edges among them ranked after e_i.  g_i is coloured greedily, ordered
+ *      by non-increasing colour, oriented into a DAG, and searched with
+ *      pruning Rules (1) and (2) of Section 4.3; a candidate set that is a
+ *      clique or a 2-plex is finished in closed form (Section 5, Algorithm
+ *      kC2Plex).
+ *
+ * Conventions
+ *   - The graph is simple and undirected (Section 2), given as int32 CSR
+ *     with both directions stored, rows strictly ascending, no self-loops.
+ *     ebbkc_prepare rejects anything else with EBBKC_E_BAD_CSR.
+ *   - An edge id is the position of the pair (u,v), u<v, in lexicographic
+ *     order.  Vertex ids are the CSR row indices.
+ *   - Every call is ordered on the given HIP stream (NULL = the null
+ *     stream); calls that return host values synchronise that stream first.
+ *   - Every call returns an ebbkc_status; nothing is thrown across this
+ *     boundary.  Outputs are written only on EBBKC_OK, except where a
+ *     function says otherwise.
+ *   - Counts are exact: a true count of 2^64 or more is reported as
+ *     EBBKC_E_OVERFLOW, never as a wrapped value.
+ *   - A handle must not be used by two calls at the same time.
+ */
+#ifndef EBBKC_H
+#define EBBKC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ebbkc_graph ebbkc_graph; /* opaque; owns its device memory */
+
+typedef enum {
+    EBBKC_OK = 0,
+    EBBKC_E_INVALID_ARG = -1,
+    EBBKC_E_BAD_CSR = -2,          /* input is not a simple undirected CSR */
+    EBBKC_E_OOM = -3,              /* device memory exhausted */
+    EBBKC_E_K_RANGE = -4,          /* k < 1 */
+    EBBKC_E_BUFFER_TOO_SMALL = -5, /* listing buffer smaller than the result */
+    EBBKC_E_OVERFLOW = -6,         /* exact count does not fit 64 bits */
+    EBBKC_E_WIDTH = -7,            /* a sub-branch exceeds the widest bitmap class */
+    EBBKC_E_HIP = -8,              /* a HIP runtime call failed */
+    EBBKC_E_CANCELLED = -9
+} ebbkc_status;
+
+enum { EBBKC_PTR_HOST = 0, EBBKC_PTR_DEVICE = 1 };
+
+/* Tuning and ablation switches.  ebbkc_default_options fills the defaults;
+ * no switch changes any count or listing. */
+typedef struct {
+    int32_t early_termination; /* 1 (default): clique / 2-plex closed forms (Section 5) */
+    int32_t t_plex;            /* largest t handled in closed form: 1 = clique only, 2 (default) */
+    int32_t rule1;             /* 1 (default): colour pruning Rule (1), Section 4.3 */
+    int32_t rule2;             /* 1 (default): colour pruning Rule (2), Section 4.3 */
+    int32_t waves_per_block;   /* workgroup size in wavefronts (default 4) */
+    int32_t blocks_per_cu;     /* persistent workgroups per compute unit (0 = auto) */
+    int32_t split_threshold;   /* root-branch work above which a seed is split (0 = auto, <0 = never) */
+    int32_t reserved[8];
+} ebbkc_options;
+
+typedef struct {
+    int32_t n;          /* vertices */
+    int64_t m;          /* undirected edges */
+    int32_t tau;        /* largest truss level (max sub-branch size bound) */
+    int32_t rounds;     /* peel rounds */
+    int32_t max_degree;
+    int64_t device_bytes; /* device memory held by the handle */
+    double prepare_ms;    /* device time of the last ebbkc_prepare */
+} ebbkc_info;
+
+enum {
+    EBBKC_LIST_SORTED = 1 /* sort the written tuples lexicographically */
+};
+
+/* Array selectors for ebbkc_export. */
+enum {
+    EBBKC_ARR_SUPPORT = 0, /* int32[m]: common neighbours of each edge in G */
+    EBBKC_ARR_RANK = 1,    /* int32[m]: position of each edge in pi_tau */
+    EBBKC_ARR_LEVEL = 2,   /* int32[m]: truss level of each edge */
+    EBBKC_ARR_SUBSIZE = 3  /* int32[m]: |V(g_i)| of each edge's sub-branch */
+};
+
+void ebbkc_default_options(ebbkc_options *opt);
+
+/* Build a handle for the graph: validate the CSR, copy it to the device
+ * (ptr_kind says where row_ptr/col_idx live), compute supports, the
+ * level-synchronous truss ordering, ranks and the rank-tagged adjacency.
+ * row_ptr: n+1 int32; col_idx: nnz int32 (nnz = 2m).  The caller keeps
+ * ownership of the input arrays; they may be freed when this returns.
+ * opt may be NULL (defaults).  On success *out owns the handle. */
+ebbkc_status ebbkc_prepare(const int32_t *row_ptr, const int32_t *col_idx, int32_t n, int64_t nnz,
+                           int32_t ptr_kind, const ebbkc_options *opt, void *stream,
+                           ebbkc_graph **out);
+
+/* Exact number of k-cliques.  k=1 gives n, k=2 gives m, k>=3 runs the
+ * edge-oriented branch and bound. */
+ebbkc_status ebbkc_count(ebbkc_graph *g, int32_t k, uint64_t *out_count, void *stream);
+
+/* Number of k-cliques whose seed edge (the edge of the clique that comes
+ * first in pi_tau) has rank in [r_begin, r_end).  Summed over a partition of
+ * [0, m) this is the full count (every k-clique is listed exactly once,
+ * Section 4.1).  k >= 3. */
+ebbkc_status ebbkc_count_range(ebbkc_graph *g, int32_t k, int64_t r_begin, int64_t r_end,
+                               uint64_t *out_count, void *stream);
+
+/* Per-seed counts for the listed edge ids (device or host arrays per
+ * ptr_kind): out[i] = number of k-cliques seeded by edge eids[i]. k >= 3. */
+ebbkc_status ebbkc_count_seeds(ebbkc_graph *g, int32_t k, const int64_t *eids, int64_t ne,
+                               int32_t ptr_kind, uint64_t *out, void *stream);
+
+/* Write every k-cliques (k >= 1) whose seed rank is in [r_begin, r_end) to
+ * d_buf (device memory, cap tuples of k int32, row-major), each tuple in
+ * ascending vertex order.  With EBBKC_LIST_SORTED the tuples are sorted
+ * lexicographically.  *out_written is the number of tuples; if it exceeds
+ * cap the call returns EBBKC_E_BUFFER_TOO_SMALL, sets *out_written to the
+ * count and writes nothing else.  out_checksums (may be NULL) receives
+ * [ordered, unordered]: with sm the SplitMix64 output function and h the
+ * fold h <- sm(h ^ t_j) over the tuple from h = k, the unordered checksum is
+ * sum_i h_i and the ordered one sum_i sm(h_i ^ sm(i)) over buffer positions
+ * i (both mod 2^64; the ordered one is meaningful with SORTED).  Pass
+ * r_begin = 0, r_end = -1 for the whole graph. */
+ebbkc_status ebbkc_list(ebbkc_graph *g, int32_t k, int64_t r_begin, int64_t r_end, int32_t *d_buf,
+                        uint64_t cap, uint32_t flags, uint64_t *out_written,
+                        uint64_t *out_checksums, void *stream);
+
+/* Copy one per-edge array (EBBKC_ARR_*) into dst (int32[m], host or device
+ * per ptr_kind). */
+ebbkc_status ebbkc_export(const ebbkc_graph *g, int32_t which, int32_t *dst, int32_t ptr_kind,
+                          void *stream);
+
+ebbkc_status ebbkc_info_get(const ebbkc_graph *g, ebbkc_info *out);
+
+/* Device time in milliseconds of the phases of the last count/list call:
+ * [0] seed selection, [1] branch kernels, [2] total. */
+ebbkc_status ebbkc_last_timing(const ebbkc_graph *g, double out_ms[4]);
+
+void ebbkc_destroy(ebbkc_graph *g);
+
+const char *ebbkc_strerror(ebbkc_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* EBBKC_H */

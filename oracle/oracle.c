@@ -822,7 +822,7 @@ int orc_seed_sizes(int32_t n, const int32_t *rp, const int32_t *ci, const int32_
  * lists over local ids 0..c-1 (plain recursion, ascending extension). */
 static int small_cliques(const uint64_t *A, int W, const uint64_t *P, int l, uint64_t *scratch,
                          uint64_t *out) {
-    return vbb_rec(A, W, P, l, 0, scratch, out);
+    return vbb_rec(A, W, P, l, 1, scratch, out);
 }
 
 /* For the listed edge ids: number of (k-2)-cliques of g_i (vertices as in

@@ -1,0 +1,244 @@
+"""EBBkC k-clique counting and listing on MI355X (gfx950) -- Python binding of libebbkc.
+
+Argument marshalling only: every step of the computation runs in the HIP kernels of
+``libebbkc.so`` (sources in ``csrc/``).  The functions below carry the names of the C entry points
+declared in ``include/ebbkc.h``; :class:`Graph` is a small convenience wrapper over a handle.
+PyTorch is used only for device memory and the current stream.  There is no CPU fallback: if the
+library is missing, loading fails with an error.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libebbkc.so")
+
+OK, E_INVALID_ARG, E_BAD_CSR, E_OOM, E_K_RANGE, E_BUFFER_TOO_SMALL, E_OVERFLOW, E_WIDTH, E_HIP, E_CANCELLED = (
+    0, -1, -2, -3, -4, -5, -6, -7, -8, -9)
+PTR_HOST, PTR_DEVICE = 0, 1
+LIST_SORTED = 1
+ARR_SUPPORT, ARR_RANK, ARR_LEVEL, ARR_SUBSIZE = 0, 1, 2, 3
+
+
+class EbbkcError(RuntimeError):
+    def __init__(self, status: int, what: str, detail: str = ""):
+        super().__init__(f"{what}: {detail} (status {status})")
+        self.status = status
+
+
+class ebbkc_options(ctypes.Structure):
+    _fields_ = [("early_termination", ctypes.c_int32), ("t_plex", ctypes.c_int32), ("rule1", ctypes.c_int32),
+                ("rule2", ctypes.c_int32), ("waves_per_block", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
+                ("split_threshold", ctypes.c_int32), ("reserved", ctypes.c_int32 * 8)]
+
+
+class ebbkc_info(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("m", ctypes.c_int64), ("tau", ctypes.c_int32), ("rounds", ctypes.c_int32),
+                ("max_degree", ctypes.c_int32), ("device_bytes", ctypes.c_int64), ("prepare_ms", ctypes.c_double)]
+
+
+EXPORTED = ("ebbkc_default_options", "ebbkc_prepare", "ebbkc_count", "ebbkc_count_range", "ebbkc_count_seeds",
+            "ebbkc_list", "ebbkc_export", "ebbkc_info_get", "ebbkc_last_timing", "ebbkc_destroy", "ebbkc_strerror")
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libebbkc.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with paper_2311_13798_amd/build.py (no CPU fallback exists)")
+    lib = ctypes.CDLL(path)
+    vp, i32, i64, u32, u64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64
+    pu64 = ctypes.POINTER(ctypes.c_uint64)
+    lib.ebbkc_default_options.argtypes = [ctypes.POINTER(ebbkc_options)]
+    lib.ebbkc_default_options.restype = None
+    lib.ebbkc_prepare.argtypes = [vp, vp, i32, i64, i32, ctypes.POINTER(ebbkc_options), vp, ctypes.POINTER(vp)]
+    lib.ebbkc_count.argtypes = [vp, i32, pu64, vp]
+    lib.ebbkc_count_range.argtypes = [vp, i32, i64, i64, pu64, vp]
+    lib.ebbkc_count_seeds.argtypes = [vp, i32, vp, i64, i32, vp, vp]
+    lib.ebbkc_list.argtypes = [vp, i32, i64, i64, vp, u64, u32, pu64, vp, vp]
+    lib.ebbkc_export.argtypes = [vp, i32, vp, i32, vp]
+    lib.ebbkc_info_get.argtypes = [vp, ctypes.POINTER(ebbkc_info)]
+    lib.ebbkc_last_timing.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
+    lib.ebbkc_destroy.argtypes = [vp]
+    lib.ebbkc_destroy.restype = None
+    lib.ebbkc_strerror.argtypes = [i32]
+    lib.ebbkc_strerror.restype = ctypes.c_char_p
+    for f in ("ebbkc_prepare", "ebbkc_count", "ebbkc_count_range", "ebbkc_count_seeds", "ebbkc_list",
+              "ebbkc_export", "ebbkc_info_get", "ebbkc_last_timing"):
+        getattr(lib, f).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(st: int, what: str):
+    if st != OK:
+        raise EbbkcError(st, what, load_library().ebbkc_strerror(st).decode())
+
+
+def _stream(stream=None):
+    if stream is not None:
+        return ctypes.c_void_p(int(stream))
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    except ImportError:  # pragma: no cover
+        pass
+    return ctypes.c_void_p(0)
+
+
+def _ptr(a):
+    """(pointer, kind) of a numpy array or torch tensor."""
+    if isinstance(a, np.ndarray):
+        return ctypes.c_void_p(a.ctypes.data), PTR_HOST
+    import torch
+    if isinstance(a, torch.Tensor):
+        return ctypes.c_void_p(a.data_ptr()), (PTR_DEVICE if a.is_cuda else PTR_HOST)
+    raise TypeError(f"unsupported array type {type(a)}")
+
+
+# ---------------------------------------------------------------- C entry points
+
+def ebbkc_default_options() -> ebbkc_options:
+    o = ebbkc_options()
+    load_library().ebbkc_default_options(ctypes.byref(o))
+    return o
+
+
+def ebbkc_prepare(row_ptr, col_idx, n: int, nnz: int, options: ebbkc_options | None = None, stream=None):
+    rp, kind = _ptr(row_ptr)
+    ci, kind2 = _ptr(col_idx)
+    if kind != kind2:
+        raise ValueError("row_ptr and col_idx must both be host or both be device arrays")
+    h = ctypes.c_void_p()
+    st = load_library().ebbkc_prepare(rp, ci, n, nnz, kind, ctypes.byref(options) if options else None,
+                                      _stream(stream), ctypes.byref(h))
+    _check(st, "ebbkc_prepare")
+    return h
+
+
+def ebbkc_count(h, k: int, stream=None) -> int:
+    out = ctypes.c_uint64()
+    _check(load_library().ebbkc_count(h, k, ctypes.byref(out), _stream(stream)), "ebbkc_count")
+    return int(out.value)
+
+
+def ebbkc_count_range(h, k: int, r_begin: int, r_end: int, stream=None) -> int:
+    out = ctypes.c_uint64()
+    _check(load_library().ebbkc_count_range(h, k, r_begin, r_end, ctypes.byref(out), _stream(stream)),
+           "ebbkc_count_range")
+    return int(out.value)
+
+
+def ebbkc_count_seeds(h, k: int, eids, out, stream=None):
+    pe, kind = _ptr(eids)
+    po, _ = _ptr(out)
+    _check(load_library().ebbkc_count_seeds(h, k, pe, len(eids), kind, po, _stream(stream)), "ebbkc_count_seeds")
+    return out
+
+
+def ebbkc_list(h, k: int, buf, cap: int, flags: int = LIST_SORTED, r_begin: int = 0, r_end: int = -1,
+               stream=None):
+    """Returns (written, ordered_checksum, unordered_checksum)."""
+    pb, kind = _ptr(buf)
+    if kind != PTR_DEVICE:
+        raise ValueError("the listing buffer must be device memory")
+    w = ctypes.c_uint64()
+    cs = (ctypes.c_uint64 * 2)()
+    st = load_library().ebbkc_list(h, k, r_begin, r_end, pb, cap, flags, ctypes.byref(w), cs, _stream(stream))
+    if st == E_BUFFER_TOO_SMALL:
+        raise EbbkcError(st, "ebbkc_list", f"buffer too small: {int(w.value)} tuples needed")
+    _check(st, "ebbkc_list")
+    return int(w.value), int(cs[0]), int(cs[1])
+
+
+def ebbkc_export(h, which: int, dst, stream=None):
+    pd, kind = _ptr(dst)
+    _check(load_library().ebbkc_export(h, which, pd, kind, _stream(stream)), "ebbkc_export")
+    return dst
+
+
+def ebbkc_info_get(h) -> ebbkc_info:
+    info = ebbkc_info()
+    _check(load_library().ebbkc_info_get(h, ctypes.byref(info)), "ebbkc_info_get")
+    return info
+
+
+def ebbkc_last_timing(h):
+    out = (ctypes.c_double * 4)()
+    _check(load_library().ebbkc_last_timing(h, out), "ebbkc_last_timing")
+    return list(out)
+
+
+def ebbkc_destroy(h):
+    load_library().ebbkc_destroy(h)
+
+
+def ebbkc_strerror(status: int) -> str:
+    return load_library().ebbkc_strerror(status).decode()
+
+
+# ---------------------------------------------------------------- convenience wrapper
+
+class Graph:
+    """A prepared graph on the current device (owns the handle)."""
+
+    def __init__(self, row_ptr, col_idx, n: int | None = None, options: ebbkc_options | None = None, stream=None,
+                 nnz: int | None = None):
+        n = int(len(row_ptr) - 1) if n is None else n
+        nnz = int(len(col_idx)) if nnz is None else nnz
+        self._h = ebbkc_prepare(row_ptr, col_idx, n, nnz, options, stream)
+        self.info = ebbkc_info_get(self._h)
+
+    @classmethod
+    def from_csr(cls, g, device: bool = True, options=None):
+        """From a graphgen.Graph-like object (n, row_ptr, col_idx numpy arrays)."""
+        if device:
+            import torch
+            rp = torch.from_numpy(np.ascontiguousarray(g.row_ptr, dtype=np.int32)).cuda()
+            nnz = int(len(g.col_idx))
+            ci = torch.from_numpy(np.ascontiguousarray(g.col_idx, dtype=np.int32)).cuda()
+            if nnz == 0:
+                ci = torch.zeros(1, dtype=torch.int32, device="cuda")
+            return cls(rp, ci, g.n, options, nnz=nnz)
+        ci = np.ascontiguousarray(g.col_idx, np.int32)
+        nnz = int(len(ci))
+        if nnz == 0:
+            ci = np.zeros(1, np.int32)
+        return cls(np.ascontiguousarray(g.row_ptr, np.int32), ci, g.n, options, nnz=nnz)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def count(self, k: int) -> int:
+        return ebbkc_count(self._h, k)
+
+    def count_range(self, k: int, r_begin: int, r_end: int) -> int:
+        return ebbkc_count_range(self._h, k, r_begin, r_end)
+
+    def export(self, which: int) -> np.ndarray:
+        out = np.zeros(max(int(self.info.m), 1), np.int32)
+        ebbkc_export(self._h, which, out)
+        return out[: int(self.info.m)]
+
+    def last_timing(self):
+        return ebbkc_last_timing(self._h)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            ebbkc_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

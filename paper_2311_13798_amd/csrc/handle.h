@@ -1,0 +1,58 @@
+// handle.h -- the prepared graph held on the device, and internal entry
+// points shared by the host-side files of libebbkc.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "../../include/ebbkc.h"
+
+struct ebbkc_graph {
+    int device = 0;
+    int32_t n = 0;
+    int64_t m = 0, nnz = 0;
+    int32_t tau = 0, rounds = 0, max_degree = 0;
+    double prepare_ms = 0.0;
+    ebbkc_options opt{};
+    int cu_count = 256;
+
+    // id-sorted CSR (input copy) and per-entry edge rank
+    int32_t* rp = nullptr;    // n+1
+    int32_t* ci = nullptr;    // nnz
+    int32_t* erank = nullptr; // nnz: rank of the edge of each entry
+    // per edge (id order)
+    int32_t* eu = nullptr;    // m, smaller endpoint
+    int32_t* ev = nullptr;    // m, larger endpoint
+    int32_t* sup0 = nullptr;  // m, common neighbours in G
+    int32_t* rank = nullptr;  // m, position in pi_tau
+    int32_t* level = nullptr; // m, truss level
+    // full rows sorted by edge rank, descending: (neighbour, rank)
+    int2* rrow = nullptr;     // nnz (row offsets = rp)
+    // degree-oriented rows sorted by edge rank, descending: (neighbour, rank)
+    int32_t* orp = nullptr;   // n+1
+    int2* orow = nullptr;     // m
+    int32_t* byrank = nullptr; // m: edge id at each rank
+    int32_t* subsize = nullptr; // m: |V(g_i)| per edge (filled on demand)
+    std::vector<int32_t> lvl_by_rank; // host copy: level of the edge at each rank (non-decreasing)
+    bool subsize_ready = false;
+
+    // per-call scratch (grown on demand, freed by destroy)
+    void* scratch = nullptr;
+    size_t scratch_bytes = 0;
+    uint64_t* d_counters = nullptr;   // small device counters
+    uint64_t* h_counters = nullptr;   // pinned mirror
+    double last_ms[4] = {0, 0, 0, 0};
+    int64_t device_bytes = 0;
+};
+
+namespace ebb {
+ebbkc_status prepare_impl(ebbkc_graph* g, const int32_t* row_ptr, const int32_t* col_idx, int32_t ptr_kind,
+                          hipStream_t s);
+ebbkc_status count_impl(ebbkc_graph* g, int32_t k, int64_t r_begin, int64_t r_end, const int64_t* d_eids,
+                        int64_t ne, uint64_t* d_per_seed, uint64_t* out, hipStream_t s);
+ebbkc_status list_impl(ebbkc_graph* g, int32_t k, int64_t r_begin, int64_t r_end, int32_t* d_buf, uint64_t cap,
+                       uint32_t flags, uint64_t* out_written, uint64_t* out_checksums, hipStream_t s);
+ebbkc_status subsize_impl(ebbkc_graph* g, hipStream_t s);
+void* scratch_get(ebbkc_graph* g, size_t bytes);
+}  // namespace ebb
