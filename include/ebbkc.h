@@ -72,7 +72,8 @@ typedef struct {
     int32_t waves_per_block;   /* workgroup size in wavefronts (default 4) */
     int32_t blocks_per_cu;     /* persistent workgroups per compute unit (0 = auto) */
     int32_t split_threshold;   /* root-branch work above which a seed is split (0 = auto, <0 = never) */
-    int32_t reserved[8];
+    int32_t count_work;        /* 1: record search work counters (ebbkc_last_work); default 0 */
+    int32_t reserved[7];
 } ebbkc_options;
 
 typedef struct {
@@ -147,9 +148,18 @@ ebbkc_status ebbkc_export(const ebbkc_graph *g, int32_t which, int32_t *dst, int
 
 ebbkc_status ebbkc_info_get(const ebbkc_graph *g, ebbkc_info *out);
 
-/* Device time in milliseconds of the phases of the last count/list call:
- * [0] seed selection, [1] branch kernels, [2] total. */
+/* Device time in milliseconds of the branch-kernel launch of each bitmap
+ * width class in the last count call: out_ms[W-1] for sub-branches of at
+ * most 64*W vertices (0 when that class was not launched), measured with HIP
+ * events on the call's stream. */
 ebbkc_status ebbkc_last_timing(const ebbkc_graph *g, double out_ms[4]);
+
+/* Search work of the last count call, filled only when the handle was
+ * prepared with ebbkc_options.count_work = 1 (otherwise zeros):
+ * [0] seeds whose sub-branch was built, [1] search nodes evaluated,
+ * [2] 64-bit word operations on candidate bitmaps (one AND + popcount of
+ * one word each), [3] reserved. */
+ebbkc_status ebbkc_last_work(const ebbkc_graph *g, uint64_t out[4]);
 
 void ebbkc_destroy(ebbkc_graph *g);
 

@@ -32,7 +32,8 @@ class EbbkcError(RuntimeError):
 class ebbkc_options(ctypes.Structure):
     _fields_ = [("early_termination", ctypes.c_int32), ("t_plex", ctypes.c_int32), ("rule1", ctypes.c_int32),
                 ("rule2", ctypes.c_int32), ("waves_per_block", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
-                ("split_threshold", ctypes.c_int32), ("reserved", ctypes.c_int32 * 8)]
+                ("split_threshold", ctypes.c_int32), ("count_work", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 7)]
 
 
 class ebbkc_info(ctypes.Structure):
@@ -41,7 +42,8 @@ class ebbkc_info(ctypes.Structure):
 
 
 EXPORTED = ("ebbkc_default_options", "ebbkc_prepare", "ebbkc_count", "ebbkc_count_range", "ebbkc_count_seeds",
-            "ebbkc_list", "ebbkc_export", "ebbkc_info_get", "ebbkc_last_timing", "ebbkc_destroy", "ebbkc_strerror")
+            "ebbkc_list", "ebbkc_export", "ebbkc_info_get", "ebbkc_last_timing", "ebbkc_last_work", "ebbkc_destroy",
+            "ebbkc_strerror")
 
 _lib = None
 
@@ -66,12 +68,13 @@ def load_library(path: str = LIB_PATH):
     lib.ebbkc_export.argtypes = [vp, i32, vp, i32, vp]
     lib.ebbkc_info_get.argtypes = [vp, ctypes.POINTER(ebbkc_info)]
     lib.ebbkc_last_timing.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
+    lib.ebbkc_last_work.argtypes = [vp, ctypes.POINTER(ctypes.c_uint64)]
     lib.ebbkc_destroy.argtypes = [vp]
     lib.ebbkc_destroy.restype = None
     lib.ebbkc_strerror.argtypes = [i32]
     lib.ebbkc_strerror.restype = ctypes.c_char_p
     for f in ("ebbkc_prepare", "ebbkc_count", "ebbkc_count_range", "ebbkc_count_seeds", "ebbkc_list",
-              "ebbkc_export", "ebbkc_info_get", "ebbkc_last_timing"):
+              "ebbkc_export", "ebbkc_info_get", "ebbkc_last_timing", "ebbkc_last_work"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -177,6 +180,12 @@ def ebbkc_last_timing(h):
     return list(out)
 
 
+def ebbkc_last_work(h):
+    out = (ctypes.c_uint64 * 4)()
+    _check(load_library().ebbkc_last_work(h, out), "ebbkc_last_work")
+    return [int(x) for x in out]
+
+
 def ebbkc_destroy(h):
     load_library().ebbkc_destroy(h)
 
@@ -231,6 +240,9 @@ class Graph:
 
     def last_timing(self):
         return ebbkc_last_timing(self._h)
+
+    def last_work(self):
+        return ebbkc_last_work(self._h)
 
     def close(self):
         if getattr(self, "_h", None):

@@ -143,4 +143,10 @@ ebbkc_status ebbkc_last_timing(const ebbkc_graph* g, double out_ms[4]) {
     return EBBKC_OK;
 }
 
+ebbkc_status ebbkc_last_work(const ebbkc_graph* g, uint64_t out[4]) {
+    if (!g || !out) return EBBKC_E_INVALID_ARG;
+    for (int i = 0; i < 4; ++i) out[i] = g->last_work[i];
+    return EBBKC_OK;
+}
+
 }  // extern "C"

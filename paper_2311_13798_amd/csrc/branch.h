@@ -7,7 +7,7 @@ namespace ebb {
 
 enum : int { ERR_WIDTH = 1, ERR_OVERFLOW = 2, ERR_DEPTH = 4, ERR_CAP = 8 };
 
-enum : int { OPT_ET = 1, OPT_TPLEX2 = 2, OPT_RULE1 = 4, OPT_RULE2 = 8 };
+enum : int { OPT_ET = 1, OPT_TPLEX2 = 2, OPT_RULE1 = 4, OPT_RULE2 = 8, OPT_WORK = 16 };
 
 constexpr int MAX_FRAMES = 24;   // search frames kept in LDS (nodes with l >= 4)
 constexpr int GLOBAL_FRAMES = 112; // further frames in device memory, per wave
@@ -44,6 +44,7 @@ struct BranchArgs {
     const uint64_t* offsets;    // per-seed first output tuple (indexed like per_seed)
     int32_t* out;               // tuples of k int32
     uint64_t cap;
+    unsigned long long* work;   // [seeds built, nodes, word ops] when OPT_WORK
     // deep-search frames (only needed when k > 2 + 2 * MAX_FRAMES + 2)
     void* gframes;              // GLOBAL_FRAMES frames per wave of the grid
 };

@@ -242,7 +242,9 @@ __global__ __launch_bounds__(256) void k_branch(BranchArgs a) {
     const int k = a.k;
     const int opts = a.opts;
     const bool rule1 = opts & OPT_RULE1, rule2 = opts & OPT_RULE2, et = opts & OPT_ET, t2 = opts & OPT_TPLEX2;
+    const bool work = opts & OPT_WORK;
     Acc acc{0, 0};
+    uint64_t wk_seeds = 0, wk_nodes = 0, wk_ops = 0;  // uniform search-work counters
 
     for (;;) {
         unsigned long long it = 0;
@@ -295,6 +297,7 @@ __global__ __launch_bounds__(256) void k_branch(BranchArgs a) {
             continue;
         }
         wave_sync();
+        wk_seeds += work;
         if (k == 3) {
             sacc.add((uint64_t)c);
             goto seed_done;
@@ -477,16 +480,19 @@ __global__ __launch_bounds__(256) void k_branch(BranchArgs a) {
             // evaluate one node: count it, or push a frame to expand it
             auto node = [&](const uint64_t (&P)[W], int l, int px, int py) {
                 int pc = popcW(P);
+                if (work) { wk_nodes += 1; wk_ops += W; }
                 if (pc < l) return;
                 if (l == 1) {
                     sacc.add((uint64_t)pc);
                     return;
                 }
                 if (l == 2) {
+                    if (work) wk_ops += (uint64_t)pc * W;
                     sacc.add(edges_in(L, P));
                     return;
                 }
                 if (et) {
+                    if (work) wk_ops += (uint64_t)pc * W;
                     int mind, nfull;
                     deg_stats(L, P, pc, mind, nfull);
                     if (mind >= pc - 1) { sacc.add(binom(pc, l)); return; }
@@ -516,7 +522,9 @@ __global__ __launch_bounds__(256) void k_branch(BranchArgs a) {
                             for (int w = 0; w < W; ++w) Uy[w] = M.rows[y][w] & upper_mask(y, w);
 #pragma unroll
                             for (int q = 0; q < W; ++q) {
-                                if ((R[q][y >> 6] >> (y & 63)) & 1) {
+                                bool act = (R[q][y >> 6] >> (y & 63)) & 1;
+                                if (work) wk_ops += (uint64_t)popc64(ballot(act)) * W;
+                                if (act) {
 #pragma unroll
                                     for (int w = 0; w < W; ++w) cnt += popc64(R[q][w] & Uy[w]);
                                 }
@@ -596,7 +604,9 @@ __global__ __launch_bounds__(256) void k_branch(BranchArgs a) {
 #pragma unroll
                 for (int w = 0; w < W; ++w) Pc[w] = R[w] & M.rows[y][w] & upper_mask(y, w);
                 int lc = l - 2;
+                if (work) wk_ops += W;
                 if (popcW(Pc) < lc) continue;
+                if (work && rule2 && lc >= 3) wk_ops += W;
                 if (rule2 && lc >= 3 && distinct_colours(L, Pc) < lc) continue;
                 node(Pc, lc, x, y);
             }
@@ -611,6 +621,11 @@ __global__ __launch_bounds__(256) void k_branch(BranchArgs a) {
             acc.hi += sacc.hi;
         }
         wave_sync();
+    }
+    if (work && lane == 0) {
+        atomicAdd(&a.work[0], (unsigned long long)wk_seeds);
+        atomicAdd(&a.work[1], (unsigned long long)wk_nodes);
+        atomicAdd(&a.work[2], (unsigned long long)wk_ops);
     }
     if (!LIST && lane == 0 && (acc.lo || acc.hi)) {
         unsigned long long old = atomicAdd(&a.total[0], (unsigned long long)acc.lo);

@@ -40,11 +40,13 @@ int opts_of(const ebbkc_options& o) {
     if (o.t_plex >= 2) f |= OPT_TPLEX2;
     if (o.rule1) f |= OPT_RULE1;
     if (o.rule2) f |= OPT_RULE2;
+    if (o.count_work) f |= OPT_WORK;
     return f;
 }
 
-// counters block: [0..MAX_W) work counters, [4,5] total lo/hi, [6] err
-constexpr int CNT_WORDS = 8;
+// counters block: [0..MAX_W) seed counters per class, [4,5] total lo/hi,
+// [6] error flags, [8..10] search work
+constexpr int CNT_WORDS = 12;
 
 }  // namespace
 
@@ -83,6 +85,7 @@ static BranchArgs base_args(ebbkc_graph* g, int32_t k) {
     a.opts = opts_of(g->opt);
     a.total = (unsigned long long*)(g->d_counters + 4);
     a.err = (int*)(g->d_counters + 6);
+    a.work = (unsigned long long*)(g->d_counters + 8);
     return a;
 }
 
@@ -96,6 +99,7 @@ static ebbkc_status finish_total(ebbkc_graph* g, uint64_t* out, hipStream_t s) {
     if (err & ERR_DEPTH) return EBBKC_E_K_RANGE;
     if ((err & ERR_OVERFLOW) || g->h_counters[5] != 0) return EBBKC_E_OVERFLOW;
     *out = g->h_counters[4];
+    for (int i = 0; i < 3; ++i) g->last_work[i] = g->h_counters[8 + i];
     return EBBKC_OK;
 }
 
@@ -133,10 +137,6 @@ ebbkc_status count_impl(ebbkc_graph* g, int32_t k, int64_t r_begin, int64_t r_en
     if (d_per_seed && r_end > r_begin)
         if (hipMemsetAsync(d_per_seed, 0, sizeof(uint64_t) * (size_t)(r_end - r_begin), s) != hipSuccess)
             return EBBKC_E_HIP;
-    hipEvent_t e0, e1;
-    (void)hipEventCreate(&e0);
-    (void)hipEventCreate(&e1);
-    (void)hipEventRecord(e0, s);
     int64_t cls[MAX_W + 1][2];
     st = class_ranges(g, k, r_begin, r_end, cls);
     if (st) return st;
@@ -155,6 +155,12 @@ ebbkc_status count_impl(ebbkc_graph* g, int32_t k, int64_t r_begin, int64_t r_en
             if (!gframes) return EBBKC_E_OOM;
         }
     }
+    hipEvent_t ev[MAX_W + 1][2] = {};
+    for (int W = 1; W <= MAX_W; ++W) {
+        g->last_ms[W - 1] = 0.0;
+        if (cls[W][1] <= cls[W][0]) continue;
+        if (hipEventCreate(&ev[W][0]) != hipSuccess || hipEventCreate(&ev[W][1]) != hipSuccess) return EBBKC_E_HIP;
+    }
     for (int W = MAX_W; W >= 1; --W) {
         int64_t a0 = cls[W][0], a1 = cls[W][1];
         if (a1 <= a0) continue;
@@ -166,17 +172,18 @@ ebbkc_status count_impl(ebbkc_graph* g, int32_t k, int64_t r_begin, int64_t r_en
         a.out_base = a0 - r_begin;
         a.per_seed = d_per_seed;
         a.next = (unsigned long long*)(g->d_counters + (W - 1));
+        (void)hipEventRecord(ev[W][0], s);
         if (launch_branch_class(W, false, a, g->cu_count, g->opt.blocks_per_cu, s) != hipSuccess) return EBBKC_E_HIP;
+        (void)hipEventRecord(ev[W][1], s);
     }
-    (void)hipEventRecord(e1, s);
     st = finish_total(g, out, s);
-    float ms = 0.f;
-    (void)hipEventElapsedTime(&ms, e0, e1);
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    g->last_ms[0] = 0.0;
-    g->last_ms[1] = ms;
-    g->last_ms[2] = ms;
+    for (int W = 1; W <= MAX_W; ++W) {
+        if (!ev[W][0]) continue;
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, ev[W][0], ev[W][1]) == hipSuccess) g->last_ms[W - 1] = ms;
+        (void)hipEventDestroy(ev[W][0]);
+        (void)hipEventDestroy(ev[W][1]);
+    }
     return st;
 }
 

@@ -43,6 +43,7 @@ struct ebbkc_graph {
     uint64_t* d_counters = nullptr;   // small device counters
     uint64_t* h_counters = nullptr;   // pinned mirror
     double last_ms[4] = {0, 0, 0, 0};
+    uint64_t last_work[4] = {0, 0, 0, 0};
     int64_t device_bytes = 0;
 };
 
