@@ -1,7 +1,7 @@
 // abi.hip -- the extern "C" boundary of libebbkc (declared in include/ebbkc.h).
 #include <new>
 
-#include "branch.h"
+#include "arena.h"
 #include "common.h"
 #include "handle.h"
 
@@ -41,7 +41,8 @@ void ebbkc_destroy(ebbkc_graph* g) {
     (void)hipGetDevice(&cur);
     (void)hipSetDevice(g->device);
     void* ptrs[] = {g->rp, g->ci, g->erank, g->eu, g->ev, g->sup0, g->rank, g->level, g->rrow, g->orp, g->orow,
-                    g->byrank, g->subsize, g->scratch, g->d_counters};
+                    g->byrank, g->subsize, g->scratch, g->d_counters, g->seed_eid, g->seed_c, g->row_off,
+                    g->vtx_off, g->arows, g->agid, g->acol, g->nedges};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (g->h_counters) (void)hipHostFree(g->h_counters);

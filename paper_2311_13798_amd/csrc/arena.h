@@ -1,0 +1,94 @@
+// arena.h -- the sub-branch arena: every seed's g_i built once per graph and
+// kept in HBM (bitmap rows in colour order, colours, global vertex ids), and
+// the task lists the search kernels pull from.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ebb {
+
+enum : int { ERR_WIDTH = 1, ERR_OVERFLOW = 2, ERR_DEPTH = 4, ERR_CAP = 8 };
+enum : int { OPT_ET = 1, OPT_TPLEX2 = 2, OPT_RULE1 = 4, OPT_RULE2 = 8, OPT_WORK = 16 };
+
+constexpr int MAX_W = 4;              // widest bitmap class: 256 vertices
+constexpr int LDS_FRAMES = 12;        // search frames kept in LDS (nodes with l >= 6)
+constexpr int GLOBAL_FRAMES = 124;    // further frames in device memory, per wave
+constexpr int MAX_K = 2 + 2 * (LDS_FRAMES + GLOBAL_FRAMES) + 4;
+
+// Graph arrays the build kernel reads.
+struct GraphView {
+    const int32_t* rp;
+    const int32_t* ci;
+    const int32_t* erank;
+    const int2* rrow;
+    const int32_t* orp;
+    const int2* orow;
+    const int32_t* eu;
+    const int32_t* ev;
+    const int32_t* rank;
+};
+
+// Seeds are the edges with |V(g_i)| >= 2 in rank order; slot s of the arena
+// holds seed s.
+struct ArenaView {
+    const int32_t* seed_eid;  // edge id of slot s
+    const int32_t* seed_c;    // |V(g_i)| of slot s
+    const int64_t* row_off;   // first 64-bit word of slot s's rows (c * W words)
+    const int64_t* vtx_off;   // first vertex entry of slot s (c entries)
+    const uint64_t* rows;     // symmetric adjacency rows, vertices in colour order
+    const int32_t* gid;       // global id of each local vertex
+    const int16_t* col;       // colour of each local vertex (non-increasing)
+};
+
+struct BuildArgs {
+    GraphView G;
+    const int32_t* list;  // slots to build (one width class)
+    int64_t n;
+    const int32_t* seed_eid;
+    const int32_t* seed_c;
+    const int64_t* row_off;
+    const int64_t* vtx_off;
+    uint64_t* rows;
+    int32_t* gid;
+    int16_t* col;
+    uint64_t* nedges;  // edges of g_i per slot
+    unsigned long long* next;
+    int* err;
+};
+
+// task = slot << 20 | x0 << 10 | x1 : the children of the root whose first
+// vertex x lies in [x0, x1)
+__host__ __device__ inline int64_t task_pack(int64_t slot, int x0, int x1) {
+    return (slot << 20) | ((int64_t)x0 << 10) | (int64_t)x1;
+}
+__host__ __device__ inline int64_t task_slot(int64_t t) { return t >> 20; }
+__host__ __device__ inline int task_x0(int64_t t) { return (int)((t >> 10) & 1023); }
+__host__ __device__ inline int task_x1(int64_t t) { return (int)(t & 1023); }
+
+struct SearchArgs {
+    ArenaView A;
+    const int64_t* tasks;
+    int64_t ntasks;
+    int32_t k;
+    int32_t opts;
+    unsigned long long* next;
+    unsigned long long* total;  // [lo, hi]
+    unsigned long long* work;   // [tasks, nodes, word ops]
+    int* err;
+    uint64_t* per_task;         // optional count per task (indexed like tasks)
+    void* gframes;              // GLOBAL_FRAMES frames per wave of the grid
+    // listing (per_task offsets of the output, tuples of k int32)
+    const uint64_t* task_off;
+    int32_t* out;
+    const int32_t* eu;
+    const int32_t* ev;
+};
+
+hipError_t launch_build(int W, const BuildArgs& a, int cus, hipStream_t s);
+hipError_t launch_search(int W, bool list, const SearchArgs& a, int cus, int blocks_per_cu, hipStream_t s);
+int64_t search_grid_waves(int W, bool list, int64_t ntasks, int cus, int blocks_per_cu);
+size_t search_frame_bytes(int W);
+hipError_t launch_binom_init(hipStream_t s);
+hipError_t launch_subsize(const GraphView& G, int64_t m, int32_t* out, hipStream_t s);
+
+}  // namespace ebb

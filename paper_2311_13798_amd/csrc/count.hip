@@ -1,24 +1,26 @@
-// count.hip -- host orchestration of the branch kernels: seed selection by
-// rank range and width class, persistent launches, exact 128-bit totals.
+// count.hip -- host orchestration of counting: the sub-branch arena, task
+// generation and the per-width-class search launches.
 //
-// Seeds.  A sub-branch of seed e_i has at most level(e_i) vertices (the peel
-// removes e_i with at most that many common neighbours among later edges), so
-// for a given k only edges with level >= k-2 can hold a k-clique.  Levels are
-// non-decreasing along the ranking, hence those seeds are one suffix of the
-// rank order, and each bitmap width class (64, 128, 192, 256 vertices) is a
-// contiguous rank interval inside it.  Classes are launched widest first and
-// each kernel hands out its seeds from the highest rank down (heaviest
-// first).
+// Seeds.  Every k-clique is counted under the edge of the clique that comes
+// first in pi_tau (Section 4.1), inside that edge's sub-branch g_i, which
+// needs at least k-2 vertices.  The arena keeps g_i for every edge with
+// |V(g_i)| >= 2, in rank order, so a rank range is a slot range.
+//
+// Tasks.  For a count at k, every slot with |V(g_i)| >= k-2 becomes one task;
+// a slot whose root has more than split_threshold (k-2)-subsets becomes one
+// task per possible first vertex x of the root's children.  Tasks are sorted
+// by bitmap width class, and inside a class by the number of vertices the
+// task's subtree can still use, largest first, so heavy work starts first.
 #include <algorithm>
+#include <cmath>
 #include <mutex>
 
-#include "branch.h"
+#include "arena.h"
 #include "common.h"
 #include "handle.h"
+#include "prims.h"
 
 namespace ebb {
-
-constexpr int MAX_W = 4;
 
 namespace {
 
@@ -44,18 +46,160 @@ int opts_of(const ebbkc_options& o) {
     return f;
 }
 
-// counters block: [0..MAX_W) seed counters per class, [4,5] total lo/hi,
-// [6] error flags, [8..10] search work
-constexpr int CNT_WORDS = 12;
+// counters: [0..4) per-class work counters, [4,5] total lo/hi, [6] error flags,
+// [8..10] search work, [12..16) per-class task counts (task generation)
+constexpr int CNT_WORDS = 16;
+
+GraphView graph_view(const ebbkc_graph* g) {
+    return GraphView{g->rp, g->ci, g->erank, g->rrow, g->orp, g->orow, g->eu, g->ev, g->rank};
+}
+
+__host__ __device__ inline int width_of(int c) { return c <= 64 ? 1 : (c <= 128 ? 2 : (c <= 192 ? 3 : 4)); }
+
+inline unsigned grid_for(int64_t n, int per = 256) {
+    int64_t b = (n + per - 1) / per;
+    if (b < 1) b = 1;
+    if (b > 16384) b = 16384;
+    return (unsigned)b;
+}
+
+// ---------------------------------------------------------------- kernels
+
+__global__ void k_seed_flags(const int32_t* __restrict__ byrank, const int32_t* __restrict__ subsize, int64_t m,
+                             int32_t* __restrict__ flag) {
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < m; r += (int64_t)gridDim.x * blockDim.x)
+        flag[r] = subsize[byrank[r]] >= 2;
+}
+
+__global__ void k_seed_fill(const int32_t* __restrict__ byrank, const int32_t* __restrict__ subsize,
+                            const int32_t* __restrict__ flag, const int64_t* __restrict__ pos, int64_t m,
+                            int32_t* __restrict__ seed_eid, int32_t* __restrict__ seed_c,
+                            int32_t* __restrict__ seed_rank, int64_t* __restrict__ rwords,
+                            int64_t* __restrict__ vcount, int* __restrict__ err) {
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < m; r += (int64_t)gridDim.x * blockDim.x) {
+        if (!flag[r]) continue;
+        const int64_t s = pos[r];
+        const int32_t e = byrank[r], c = subsize[e];
+        if (c > 64 * MAX_W) atomicOr(err, ERR_WIDTH);
+        seed_eid[s] = e;
+        seed_c[s] = c;
+        seed_rank[s] = (int32_t)r;
+        rwords[s] = (int64_t)c * width_of(c);
+        vcount[s] = c;
+    }
+}
+
+// slots of one width class, in slot order
+__global__ void k_class_flags(const int32_t* __restrict__ seed_c, int64_t n, int W, int32_t* __restrict__ flag) {
+    for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < n; s += (int64_t)gridDim.x * blockDim.x)
+        flag[s] = width_of(seed_c[s]) == W;
+}
+
+__global__ void k_class_fill(const int32_t* __restrict__ flag, const int64_t* __restrict__ pos, int64_t n,
+                             int32_t* __restrict__ list) {
+    for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < n; s += (int64_t)gridDim.x * blockDim.x)
+        if (flag[s]) list[pos[s]] = (int32_t)s;
+}
+
+// is the root of a slot with c vertices split at l0 = k-2?  (log C(c, l0) > log threshold)
+__device__ __forceinline__ bool split_root(int c, int l0, double log_threshold) {
+    if (l0 < 4 || c < l0 + 8) return false;
+    const double lc = lgamma((double)c + 1) - lgamma((double)l0 + 1) - lgamma((double)(c - l0) + 1);
+    return lc > log_threshold;
+}
+
+__global__ void k_task_counts(const int32_t* __restrict__ seed_c, int64_t i0, int64_t n, int l0, double log_thr,
+                              int32_t* __restrict__ tcount) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int c = seed_c[i0 + i];
+        int t = 0;
+        if (c >= l0) t = split_root(c, l0, log_thr) ? c - l0 + 1 : 1;
+        tcount[i] = t;
+    }
+}
+
+__global__ void k_task_fill(const int32_t* __restrict__ seed_c, int64_t i0, int64_t n, int l0, double log_thr,
+                            const int64_t* __restrict__ toff, int64_t* __restrict__ tasks, uint64_t* __restrict__ keys,
+                            uint32_t* __restrict__ vals, unsigned long long* __restrict__ cls_count) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int c = seed_c[i0 + i];
+        if (c < l0) continue;
+        const int W = width_of(c);
+        int64_t o = toff[i];
+        if (split_root(c, l0, log_thr)) {
+            for (int x = 0; x <= c - l0; ++x, ++o) {
+                tasks[o] = task_pack(i0 + i, x, x + 1);
+                keys[o] = ((uint64_t)(W - 1) << 8) | (uint64_t)(255 - (c - 1 - x));
+                vals[o] = (uint32_t)o;
+            }
+            atomicAdd(&cls_count[W - 1], (unsigned long long)(c - l0 + 1));
+        } else {
+            tasks[o] = task_pack(i0 + i, 0, c);
+            keys[o] = ((uint64_t)(W - 1) << 8) | (uint64_t)(255 - (c > 255 ? 255 : c));
+            vals[o] = (uint32_t)o;
+            atomicAdd(&cls_count[W - 1], 1ull);
+        }
+    }
+}
+
+__global__ void k_gather_tasks(const int64_t* __restrict__ tasks, const uint32_t* __restrict__ idx, int64_t n,
+                               int64_t* __restrict__ out) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = tasks[idx[i]];
+}
+
+// sum of a per-item value over [lo, hi): k = 3 sums |V(g_i)| by rank, k = 4 |E(g_i)| by slot
+__global__ void k_sum_range(const int32_t* __restrict__ byrank, const int32_t* __restrict__ vals32,
+                            const uint64_t* __restrict__ vals64, int64_t lo, int64_t hi,
+                            unsigned long long* __restrict__ out) {
+    uint64_t acc = 0;
+    for (int64_t i = lo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < hi; i += (int64_t)gridDim.x * blockDim.x)
+        acc += vals32 ? (uint64_t)vals32[byrank ? byrank[i] : i] : vals64[i];
+    acc = wave_sum(acc);
+    if (lane_id() == 0 && acc) atomicAdd(out, (unsigned long long)acc);
+}
+
+// bump allocator over one scratch buffer
+struct Carve {
+    char* base;
+    size_t used, cap;
+    template <typename T>
+    T* take(int64_t n) {
+        const size_t bytes = ((sizeof(T) * (size_t)(n > 0 ? n : 1)) + 255) & ~(size_t)255;
+        if (!base || used + bytes > cap) return nullptr;
+        T* p = reinterpret_cast<T*>(base + used);
+        used += bytes;
+        return p;
+    }
+};
+
+inline size_t rnd256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+template <typename T>
+struct DBuf {
+    T* p = nullptr;
+    hipError_t alloc(int64_t n) { return hipMalloc((void**)&p, sizeof(T) * (size_t)(n > 0 ? n : 1)); }
+    ~DBuf() { if (p) (void)hipFree(p); }
+    T* release() { T* q = p; p = nullptr; return q; }
+};
 
 }  // namespace
+
+#define CHKH(expr)                                                              \
+    do {                                                                        \
+        hipError_t e_ = (expr);                                                 \
+        if (e_ != hipSuccess) {                                                 \
+            (void)hipGetLastError();                                            \
+            return e_ == hipErrorOutOfMemory ? EBBKC_E_OOM : EBBKC_E_HIP;       \
+        }                                                                       \
+    } while (0)
 
 void* scratch_get(ebbkc_graph* g, size_t bytes) {
     if (bytes <= g->scratch_bytes) return g->scratch;
     if (g->scratch) (void)hipFree(g->scratch);
     g->scratch = nullptr;
     g->scratch_bytes = 0;
-    size_t nb = bytes + bytes / 4;
+    const size_t nb = bytes + bytes / 4;
     if (hipMalloc(&g->scratch, nb) != hipSuccess) return nullptr;
     g->scratch_bytes = nb;
     return g->scratch;
@@ -70,31 +214,128 @@ static ebbkc_status ensure_counters(ebbkc_graph* g) {
     return EBBKC_OK;
 }
 
-static BranchArgs base_args(ebbkc_graph* g, int32_t k) {
-    BranchArgs a{};
-    a.rp = g->rp;
-    a.ci = g->ci;
-    a.erank = g->erank;
-    a.rrow = g->rrow;
-    a.orp = g->orp;
-    a.orow = g->orow;
-    a.eu = g->eu;
-    a.ev = g->ev;
-    a.rank = g->rank;
-    a.k = k;
-    a.opts = opts_of(g->opt);
-    a.total = (unsigned long long*)(g->d_counters + 4);
-    a.err = (int*)(g->d_counters + 6);
-    a.work = (unsigned long long*)(g->d_counters + 8);
-    return a;
+ebbkc_status subsize_impl(ebbkc_graph* g, hipStream_t s) {
+    if (g->subsize_ready) return EBBKC_OK;
+    if (!g->subsize && hipMalloc((void**)&g->subsize, sizeof(int32_t) * (size_t)(g->m > 0 ? g->m : 1)) != hipSuccess)
+        return EBBKC_E_OOM;
+    CHKH(launch_subsize(graph_view(g), g->m, g->subsize, s));
+    g->subsize_ready = true;
+    return EBBKC_OK;
 }
 
-static ebbkc_status finish_total(ebbkc_graph* g, uint64_t* out, hipStream_t s) {
-    if (hipMemcpyAsync(g->h_counters, g->d_counters, CNT_WORDS * sizeof(uint64_t), hipMemcpyDeviceToHost, s) !=
-        hipSuccess)
-        return EBBKC_E_HIP;
-    if (hipStreamSynchronize(s) != hipSuccess) return EBBKC_E_HIP;
-    int err = (int)g->h_counters[6];
+ebbkc_status arena_impl(ebbkc_graph* g, hipStream_t s) {
+    if (g->arena_built) return EBBKC_OK;
+    ebbkc_status st = ensure_counters(g);
+    if (st) return st;
+    hipEvent_t e0, e1;
+    CHKH(hipEventCreate(&e0));
+    CHKH(hipEventCreate(&e1));
+    CHKH(hipEventRecord(e0, s));
+    st = subsize_impl(g, s);
+    if (st) return st;
+    const int64_t m = g->m;
+    DBuf<int32_t> flag, srank;
+    DBuf<int64_t> pos, tmp, rwords, vcount;
+    CHKH(flag.alloc(m));
+    CHKH(pos.alloc(m + 1));
+    CHKH(tmp.alloc(scan_tmp_elems(m + 1) + 64));
+    CHKH(hipMemsetAsync(g->d_counters, 0, CNT_WORDS * sizeof(uint64_t), s));
+    int* err = (int*)(g->d_counters + 6);
+    if (m) hipLaunchKernelGGL(k_seed_flags, dim3(grid_for(m)), dim3(256), 0, s, g->byrank, g->subsize, m, flag.p);
+    CHKH(exclusive_scan_i32(flag.p, pos.p, m, pos.p + m, tmp.p, s));
+    int64_t ns = 0;
+    CHKH(hipMemcpyAsync(&ns, pos.p + m, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    CHKH(hipStreamSynchronize(s));
+    DBuf<int32_t> seid, sc;
+    DBuf<int64_t> roff, voff;
+    CHKH(seid.alloc(ns));
+    CHKH(sc.alloc(ns));
+    CHKH(srank.alloc(ns));
+    CHKH(rwords.alloc(ns + 1));
+    CHKH(vcount.alloc(ns + 1));
+    CHKH(roff.alloc(ns + 1));
+    CHKH(voff.alloc(ns + 1));
+    if (m)
+        hipLaunchKernelGGL(k_seed_fill, dim3(grid_for(m)), dim3(256), 0, s, g->byrank, g->subsize, flag.p, pos.p, m,
+                           seid.p, sc.p, srank.p, rwords.p, vcount.p, err);
+    CHKH(exclusive_scan_i64(rwords.p, roff.p, ns, roff.p + ns, tmp.p, s));
+    CHKH(exclusive_scan_i64(vcount.p, voff.p, ns, voff.p + ns, tmp.p, s));
+    int64_t tot[2] = {0, 0};
+    int herr = 0;
+    CHKH(hipMemcpyAsync(&tot[0], roff.p + ns, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    CHKH(hipMemcpyAsync(&tot[1], voff.p + ns, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    CHKH(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, s));
+    g->seed_rank_host.resize((size_t)ns);
+    if (ns) CHKH(hipMemcpyAsync(g->seed_rank_host.data(), srank.p, sizeof(int32_t) * ns, hipMemcpyDeviceToHost, s));
+    CHKH(hipStreamSynchronize(s));
+    if (herr & ERR_WIDTH) return EBBKC_E_WIDTH;
+    DBuf<uint64_t> rows, ned;
+    DBuf<int32_t> gid;
+    DBuf<int16_t> col;
+    CHKH(rows.alloc(tot[0]));
+    CHKH(gid.alloc(tot[1]));
+    CHKH(col.alloc(tot[1]));
+    CHKH(ned.alloc(ns));
+    // per width class: the slot list, then the build kernel
+    DBuf<int32_t> cflag, clist;
+    DBuf<int64_t> cpos;
+    CHKH(cflag.alloc(ns));
+    CHKH(clist.alloc(ns));
+    CHKH(cpos.alloc(ns + 1));
+    for (int W = MAX_W; W >= 1 && ns > 0; --W) {
+        hipLaunchKernelGGL(k_class_flags, dim3(grid_for(ns)), dim3(256), 0, s, sc.p, ns, W, cflag.p);
+        CHKH(exclusive_scan_i32(cflag.p, cpos.p, ns, cpos.p + ns, tmp.p, s));
+        hipLaunchKernelGGL(k_class_fill, dim3(grid_for(ns)), dim3(256), 0, s, cflag.p, cpos.p, ns, clist.p);
+        int64_t nw = 0;
+        CHKH(hipMemcpyAsync(&nw, cpos.p + ns, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        CHKH(hipStreamSynchronize(s));
+        if (!nw) continue;
+        CHKH(hipMemsetAsync(g->d_counters + W - 1, 0, sizeof(uint64_t), s));
+        BuildArgs b{};
+        b.G = graph_view(g);
+        b.list = clist.p;
+        b.n = nw;
+        b.seed_eid = seid.p;
+        b.seed_c = sc.p;
+        b.row_off = roff.p;
+        b.vtx_off = voff.p;
+        b.rows = rows.p;
+        b.gid = gid.p;
+        b.col = col.p;
+        b.nedges = ned.p;
+        b.next = (unsigned long long*)(g->d_counters + W - 1);
+        b.err = err;
+        CHKH(launch_build(W, b, g->cu_count, s));
+        CHKH(hipStreamSynchronize(s));  // clist is reused by the next class
+    }
+    CHKH(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, s));
+    CHKH(hipEventRecord(e1, s));
+    CHKH(hipStreamSynchronize(s));
+    if (herr & ERR_WIDTH) return EBBKC_E_WIDTH;
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    g->arena_ms = ms;
+    g->nseeds = ns;
+    g->seed_eid = seid.release();
+    g->seed_c = sc.release();
+    g->row_off = roff.release();
+    g->vtx_off = voff.release();
+    g->arows = rows.release();
+    g->agid = gid.release();
+    g->acol = col.release();
+    g->nedges = ned.release();
+    g->arena_bytes = (int64_t)(tot[0] * 8 + tot[1] * 6 + ns * 32);
+    g->device_bytes += g->arena_bytes;
+    g->arena_built = true;
+    return EBBKC_OK;
+}
+
+static ebbkc_status read_total(ebbkc_graph* g, uint64_t* out, hipStream_t s) {
+    CHKH(hipMemcpyAsync(g->h_counters, g->d_counters, CNT_WORDS * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+    CHKH(hipStreamSynchronize(s));
+    const int err = (int)g->h_counters[6];
     if (err & ERR_WIDTH) return EBBKC_E_WIDTH;
     if (err & ERR_DEPTH) return EBBKC_E_K_RANGE;
     if ((err & ERR_OVERFLOW) || g->h_counters[5] != 0) return EBBKC_E_OVERFLOW;
@@ -103,80 +344,153 @@ static ebbkc_status finish_total(ebbkc_graph* g, uint64_t* out, hipStream_t s) {
     return EBBKC_OK;
 }
 
-// Rank interval [lo, hi) of seeds able to hold a k-clique, split by width
-// class; cls[W] = [lo_W, hi_W).
-static ebbkc_status class_ranges(const ebbkc_graph* g, int32_t k, int64_t lo, int64_t hi, int64_t cls[MAX_W + 1][2]) {
-    const auto& L = g->lvl_by_rank;
-    int64_t first = std::lower_bound(L.begin(), L.end(), k - 2) - L.begin();
-    if (lo < first) lo = first;
-    for (int W = 0; W <= MAX_W; ++W) cls[W][0] = cls[W][1] = 0;
-    if (lo >= hi) return EBBKC_OK;
-    if (L[(size_t)hi - 1] > 64 * MAX_W) return EBBKC_E_WIDTH;
-    for (int W = 1; W <= MAX_W; ++W) {
-        int64_t a = W == 1 ? 0 : std::lower_bound(L.begin(), L.end(), 64 * (W - 1) + 1) - L.begin();
-        int64_t b = std::lower_bound(L.begin(), L.end(), 64 * W + 1) - L.begin();
-        a = std::max(a, lo);
-        b = std::min(b, hi);
-        if (b > a) { cls[W][0] = a; cls[W][1] = b; }
-    }
+// Task list of slots [i0, i1) at l0 = k-2, sorted (width class, heaviest
+// first) into `sorted`; class sizes into ccount.  Scratch comes from cv.
+static ebbkc_status make_tasks(ebbkc_graph* g, int64_t i0, int64_t n, int l0, double log_thr, hipStream_t s,
+                               Carve& cv, int64_t** sorted, int64_t* T_out, uint64_t ccount[4]) {
+    int32_t* tcount = cv.take<int32_t>(n);
+    int64_t* toff = cv.take<int64_t>(n + 1);
+    int64_t* tmp = cv.take<int64_t>(scan_tmp_elems(n + 1) + 64);
+    if (!tcount || !toff || !tmp) return EBBKC_E_OOM;
+    hipLaunchKernelGGL(k_task_counts, dim3(grid_for(n)), dim3(256), 0, s, g->seed_c, i0, n, l0, log_thr, tcount);
+    CHKH(exclusive_scan_i32(tcount, toff, n, toff + n, tmp, s));
+    int64_t T = 0;
+    CHKH(hipMemcpyAsync(&T, toff + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    CHKH(hipStreamSynchronize(s));
+    *T_out = T;
+    if (T == 0) return EBBKC_OK;
+    if (T >= ((int64_t)1 << 32)) return EBBKC_E_OOM;
+    const int64_t hn = radix_hist_elems(T);
+    int64_t* tasks = cv.take<int64_t>(T);
+    int64_t* tsorted = cv.take<int64_t>(T);
+    uint64_t* keys = cv.take<uint64_t>(T);
+    uint64_t* keys2 = cv.take<uint64_t>(T);
+    uint32_t* vals = cv.take<uint32_t>(T);
+    uint32_t* vals2 = cv.take<uint32_t>(T);
+    int64_t* hist = cv.take<int64_t>(hn);
+    int64_t* htmp = cv.take<int64_t>(scan_tmp_elems(hn) + 64);
+    if (!tasks || !tsorted || !keys || !keys2 || !vals || !vals2 || !hist || !htmp) return EBBKC_E_OOM;
+    unsigned long long* cls_count = (unsigned long long*)(g->d_counters + 12);
+    CHKH(hipMemsetAsync(cls_count, 0, 4 * sizeof(uint64_t), s));
+    hipLaunchKernelGGL(k_task_fill, dim3(grid_for(n)), dim3(256), 0, s, g->seed_c, i0, n, l0, log_thr, toff, tasks,
+                       keys, vals, cls_count);
+    CHKH(radix_sort_u64(keys, vals, keys2, vals2, T, 10, hist, htmp, s));
+    hipLaunchKernelGGL(k_gather_tasks, dim3(grid_for(T)), dim3(256), 0, s, tasks, vals, T, tsorted);
+    CHKH(hipGetLastError());
+    CHKH(hipMemcpyAsync(ccount, cls_count, 4 * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+    CHKH(hipStreamSynchronize(s));
+    *sorted = tsorted;
     return EBBKC_OK;
+}
+
+// scratch bytes for make_tasks over n slots with at most T tasks
+static size_t task_bytes(int64_t n, int64_t T) {
+    const int64_t hn = radix_hist_elems(T);
+    return rnd256((size_t)n * 4) + rnd256((size_t)(n + 1) * 8) + rnd256((size_t)(scan_tmp_elems(n + 1) + 64) * 8) +
+           4 * rnd256((size_t)T * 8) + 2 * rnd256((size_t)T * 4) + rnd256((size_t)hn * 8) +
+           rnd256((size_t)(scan_tmp_elems(hn) + 64) * 8) + 4096;
 }
 
 ebbkc_status count_impl(ebbkc_graph* g, int32_t k, int64_t r_begin, int64_t r_end, const int64_t* d_eids, int64_t ne,
                         uint64_t* d_per_seed, uint64_t* out, hipStream_t s) {
     (void)d_eids;
     (void)ne;
-    if (k < 1) return EBBKC_E_K_RANGE;
-    if (k > MAX_K) return EBBKC_E_K_RANGE;
+    (void)d_per_seed;
+    if (k < 3 || k > MAX_K) return EBBKC_E_K_RANGE;
     ebbkc_status st = ensure_counters(g);
     if (st) return st;
     if (ensure_binom(g->device, s) != hipSuccess) return EBBKC_E_HIP;
     if (r_end < 0 || r_end > g->m) r_end = g->m;
     if (r_begin < 0) r_begin = 0;
-    if (hipMemsetAsync(g->d_counters, 0, CNT_WORDS * sizeof(uint64_t), s) != hipSuccess) return EBBKC_E_HIP;
-    if (d_per_seed && r_end > r_begin)
-        if (hipMemsetAsync(d_per_seed, 0, sizeof(uint64_t) * (size_t)(r_end - r_begin), s) != hipSuccess)
-            return EBBKC_E_HIP;
-    int64_t cls[MAX_W + 1][2];
-    st = class_ranges(g, k, r_begin, r_end, cls);
+    for (int i = 0; i < 4; ++i) g->last_ms[i] = 0.0;
+    for (int i = 0; i < 4; ++i) g->last_work[i] = 0;
+    CHKH(hipMemsetAsync(g->d_counters, 0, CNT_WORDS * sizeof(uint64_t), s));
+    unsigned long long* total = (unsigned long long*)(g->d_counters + 4);
+    if (k == 3) {  // sum of |V(g_i)| over the seeds
+        st = subsize_impl(g, s);
+        if (st) return st;
+        if (r_end > r_begin)
+            hipLaunchKernelGGL(k_sum_range, dim3(grid_for(r_end - r_begin)), dim3(256), 0, s, g->byrank, g->subsize,
+                               (const uint64_t*)nullptr, r_begin, r_end, total);
+        CHKH(hipGetLastError());
+        return read_total(g, out, s);
+    }
+    st = arena_impl(g, s);
     if (st) return st;
-    // deep searches need frames in device memory: one allocation for all classes
-    void* gframes = nullptr;
-    if (k > 2 + 2 * MAX_FRAMES + 2) {
-        size_t need = 0;
-        for (int W = 1; W <= MAX_W; ++W) {
-            if (cls[W][1] <= cls[W][0]) continue;
-            int64_t waves = branch_grid_waves(W, cls[W][1] - cls[W][0], g->cu_count, g->opt.blocks_per_cu);
-            if (waves < 0) return EBBKC_E_HIP;
-            need = std::max(need, (size_t)waves * GLOBAL_FRAMES * branch_frame_bytes(W));
-        }
-        if (need) {
-            gframes = scratch_get(g, need);
-            if (!gframes) return EBBKC_E_OOM;
-        }
+    CHKH(hipMemsetAsync(g->d_counters, 0, CNT_WORDS * sizeof(uint64_t), s));
+    const auto& SR = g->seed_rank_host;
+    const int64_t i0 =
+        std::lower_bound(SR.begin(), SR.end(), (int32_t)std::min<int64_t>(r_begin, INT32_MAX)) - SR.begin();
+    const int64_t i1 =
+        std::lower_bound(SR.begin(), SR.end(), (int32_t)std::min<int64_t>(r_end, INT32_MAX)) - SR.begin();
+    const int64_t n = i1 - i0;
+    if (k == 4) {  // sum of |E(g_i)| over the seeds
+        if (n > 0)
+            hipLaunchKernelGGL(k_sum_range, dim3(grid_for(n)), dim3(256), 0, s, (const int32_t*)nullptr,
+                               (const int32_t*)nullptr, g->nedges, i0, i1, total);
+        CHKH(hipGetLastError());
+        return read_total(g, out, s);
     }
+    if (n <= 0) return read_total(g, out, s);
+    const int l0 = k - 2;
+    const double thr = g->opt.split_threshold > 0 ? (double)g->opt.split_threshold : (double)(1 << 22);
+    const double log_thr = g->opt.split_threshold < 0 ? 1e300 : std::log(thr);
+
+    // ---- tasks (the scratch is sized for the worst case: every slot split)
+    const int64_t Tmax = n * (int64_t)(64 * MAX_W);
+    const bool deep = k > 2 + 2 * LDS_FRAMES + 4;
+    int64_t waves_max = 0;
+    for (int W = 1; W <= MAX_W; ++W)
+        waves_max = std::max(waves_max, search_grid_waves(W, false, Tmax, g->cu_count, g->opt.blocks_per_cu));
+    const size_t fbytes = deep ? (size_t)waves_max * GLOBAL_FRAMES * search_frame_bytes(MAX_W) : 0;
+    // count the real number of tasks first with a small scratch, then size
+    Carve cv0{(char*)scratch_get(g, task_bytes(n, 1)), 0, 0};
+    cv0.cap = g->scratch_bytes;
+    int32_t* tcount = cv0.take<int32_t>(n);
+    int64_t* toff = cv0.take<int64_t>(n + 1);
+    int64_t* tmp = cv0.take<int64_t>(scan_tmp_elems(n + 1) + 64);
+    if (!tcount || !toff || !tmp) return EBBKC_E_OOM;
+    hipLaunchKernelGGL(k_task_counts, dim3(grid_for(n)), dim3(256), 0, s, g->seed_c, i0, n, l0, log_thr, tcount);
+    CHKH(exclusive_scan_i32(tcount, toff, n, toff + n, tmp, s));
+    int64_t T = 0;
+    CHKH(hipMemcpyAsync(&T, toff + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    CHKH(hipStreamSynchronize(s));
+    if (T == 0) return read_total(g, out, s);
+    if (!scratch_get(g, task_bytes(n, T) + rnd256(fbytes))) return EBBKC_E_OOM;
+    Carve cv{(char*)g->scratch, 0, g->scratch_bytes};
+    int64_t* tsorted = nullptr;
+    uint64_t ccount[4] = {0, 0, 0, 0};
+    int64_t T2 = 0;
+    st = make_tasks(g, i0, n, l0, log_thr, s, cv, &tsorted, &T2, ccount);
+    if (st) return st;
+    void* gframes = deep ? (void*)cv.take<char>((int64_t)fbytes) : nullptr;
+    if (deep && !gframes) return EBBKC_E_OOM;
+
+    // ---- search, one launch per width class (classes are contiguous in tsorted)
     hipEvent_t ev[MAX_W + 1][2] = {};
+    int64_t off = 0;
     for (int W = 1; W <= MAX_W; ++W) {
-        g->last_ms[W - 1] = 0.0;
-        if (cls[W][1] <= cls[W][0]) continue;
-        if (hipEventCreate(&ev[W][0]) != hipSuccess || hipEventCreate(&ev[W][1]) != hipSuccess) return EBBKC_E_HIP;
-    }
-    for (int W = MAX_W; W >= 1; --W) {
-        int64_t a0 = cls[W][0], a1 = cls[W][1];
-        if (a1 <= a0) continue;
-        BranchArgs a = base_args(g, k);
+        const int64_t nt = (int64_t)ccount[W - 1];
+        if (!nt) continue;
+        CHKH(hipEventCreate(&ev[W][0]));
+        CHKH(hipEventCreate(&ev[W][1]));
+        SearchArgs a{};
+        a.A = ArenaView{g->seed_eid, g->seed_c, g->row_off, g->vtx_off, g->arows, g->agid, g->acol};
+        a.tasks = tsorted + off;
+        a.ntasks = nt;
+        a.k = k;
+        a.opts = opts_of(g->opt);
+        a.next = (unsigned long long*)(g->d_counters + W - 1);
+        a.total = total;
+        a.work = (unsigned long long*)(g->d_counters + 8);
+        a.err = (int*)(g->d_counters + 6);
         a.gframes = gframes;
-        a.seeds = g->byrank + a0;
-        a.nseeds = a1 - a0;
-        a.reverse = 1;
-        a.out_base = a0 - r_begin;
-        a.per_seed = d_per_seed;
-        a.next = (unsigned long long*)(g->d_counters + (W - 1));
-        (void)hipEventRecord(ev[W][0], s);
-        if (launch_branch_class(W, false, a, g->cu_count, g->opt.blocks_per_cu, s) != hipSuccess) return EBBKC_E_HIP;
-        (void)hipEventRecord(ev[W][1], s);
+        CHKH(hipEventRecord(ev[W][0], s));
+        CHKH(launch_search(W, false, a, g->cu_count, g->opt.blocks_per_cu, s));
+        CHKH(hipEventRecord(ev[W][1], s));
+        off += nt;
     }
-    st = finish_total(g, out, s);
+    st = read_total(g, out, s);
     for (int W = 1; W <= MAX_W; ++W) {
         if (!ev[W][0]) continue;
         float ms = 0.f;
@@ -185,16 +499,6 @@ ebbkc_status count_impl(ebbkc_graph* g, int32_t k, int64_t r_begin, int64_t r_en
         (void)hipEventDestroy(ev[W][1]);
     }
     return st;
-}
-
-ebbkc_status subsize_impl(ebbkc_graph* g, hipStream_t s) {
-    if (g->subsize_ready) return EBBKC_OK;
-    if (!g->subsize && hipMalloc((void**)&g->subsize, sizeof(int32_t) * (size_t)(g->m > 0 ? g->m : 1)) != hipSuccess)
-        return EBBKC_E_OOM;
-    if (launch_subsize(g->rp, g->ci, g->erank, g->rrow, g->eu, g->ev, g->rank, g->m, g->subsize, s) != hipSuccess)
-        return EBBKC_E_HIP;
-    g->subsize_ready = true;
-    return EBBKC_OK;
 }
 
 }  // namespace ebb

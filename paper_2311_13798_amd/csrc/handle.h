@@ -37,6 +37,21 @@ struct ebbkc_graph {
     std::vector<int32_t> lvl_by_rank; // host copy: level of the edge at each rank (non-decreasing)
     bool subsize_ready = false;
 
+    // sub-branch arena (built on the first count with k >= 4)
+    bool arena_built = false;
+    int64_t nseeds = 0;          // edges with |V(g_i)| >= 2, in rank order
+    int32_t* seed_eid = nullptr;
+    int32_t* seed_c = nullptr;
+    int64_t* row_off = nullptr;
+    int64_t* vtx_off = nullptr;
+    uint64_t* arows = nullptr;
+    int32_t* agid = nullptr;
+    int16_t* acol = nullptr;
+    uint64_t* nedges = nullptr;
+    int64_t arena_bytes = 0;
+    std::vector<int32_t> seed_rank_host; // rank of each slot (ascending)
+    double arena_ms = 0.0;
+
     // per-call scratch (grown on demand, freed by destroy)
     void* scratch = nullptr;
     size_t scratch_bytes = 0;
@@ -55,5 +70,6 @@ ebbkc_status count_impl(ebbkc_graph* g, int32_t k, int64_t r_begin, int64_t r_en
 ebbkc_status list_impl(ebbkc_graph* g, int32_t k, int64_t r_begin, int64_t r_end, int32_t* d_buf, uint64_t cap,
                        uint32_t flags, uint64_t* out_written, uint64_t* out_checksums, hipStream_t s);
 ebbkc_status subsize_impl(ebbkc_graph* g, hipStream_t s);
+ebbkc_status arena_impl(ebbkc_graph* g, hipStream_t s);
 void* scratch_get(ebbkc_graph* g, size_t bytes);
 }  // namespace ebb

@@ -213,8 +213,16 @@ __global__ void k_peel_flag(const int32_t* __restrict__ live, int64_t nlive, con
         flag[i] = x <= s;
         mn = x < mn ? x : mn;
     }
+    // one atomic per block
+    __shared__ int32_t bm[TB / EBB_WAVE];
     mn = wave_min(mn);
-    if (lane_id() == 0) atomicMin(&st->minsup, mn);
+    if (lane_id() == 0) bm[threadIdx.x / EBB_WAVE] = mn;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < TB / EBB_WAVE; ++i) mn = bm[i] < mn ? bm[i] : mn;
+        mn = bm[0] < mn ? bm[0] : mn;
+        if (mn < 0x7fffffff) atomicMin(&st->minsup, mn);
+    }
 }
 
 __global__ void k_peel_compact(const int32_t* __restrict__ live, int64_t nlive, const int32_t* __restrict__ flag,
@@ -445,8 +453,8 @@ ebbkc_status prepare_impl(ebbkc_graph* g, const int32_t* row_ptr, const int32_t*
     int64_t nlive = m, ranked = 0;
     int32_t lev = 0, r = 0, maxlev = 0;
     while (ranked < m) {
-        unsigned gl = grid_for(nlive);
-        if (gl > 8192) gl = 8192;
+        unsigned gl = grid_for(nlive, TB * 8);  // about eight entries per thread
+        if (gl > 2048) gl = 2048;
         hipLaunchKernelGGL(k_peel_reset, dim3(1), dim3(1), 0, s, st.p);
         hipLaunchKernelGGL(k_peel_flag, dim3(gl), dim3(TB), 0, s, live.p, nlive, sup.p, lev, flag.p, st.p);
         CHK(exclusive_scan_i32(flag.p, pos.p, nlive, &st.p->nf, scan_tmp.p, s));

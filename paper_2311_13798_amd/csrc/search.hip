@@ -1,0 +1,553 @@
+// search.hip -- the EBBkC-C_Rec search over arena sub-branches (one
+// wavefront per task).
+//
+// A task is a seed's g_i (from the arena) and a range [x0, x1) of first
+// vertices of the root's children; light seeds are one task, heavy seeds one
+// task per root vertex.  On the DAG of g_i (vertices in colour order, edges
+// low -> high) a node (P, l):
+//   * is pruned when |P| < l (Algorithm EBBkC);
+//   * at l = 1 counts |P|, at l = 2 the edges inside P;
+//   * at l >= 3 is finished in closed form when P is a clique, C(|P|, l), or
+//     a 2-plex, sum_j C(p, j) 2^j C(f, l-j) with f full vertices and p
+//     non-adjacent pairs (Section 5, Algorithm kC2Plex);
+//   * at l = 3 counts the triangles inside P;
+//   * otherwise branches on every DAG edge x->y inside P into
+//     P' = P & N+(x) & N+(y), l-2, skipping children by Rule (1)
+//     (col x < l or col y < l-1) and Rule (2) (fewer than l-2 colours in P')
+//     (Section 4.3, Algorithm EBBkC-C).
+// Nodes with l = 4 or 5 hand their children (l = 2 or 3) to lanes, one child
+// per lane; everything above is wave-uniform with the lanes owning rows.
+#include "arena.h"
+#include "device_util.h"
+
+namespace ebb {
+
+// C(n, r) for n < BIN_N, r < BIN_R, saturated to UINT64_MAX when it does not fit
+constexpr int BIN_N = 1025, BIN_R = 65;
+__device__ uint64_t g_binom[BIN_N * BIN_R];
+
+__global__ void k_binom_init() {
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= BIN_N) return;
+    unsigned __int128 c = 1;
+    bool sat = false;
+    g_binom[n * BIN_R + 0] = 1;
+    for (int r = 1; r < BIN_R; ++r) {
+        if (r > n) { g_binom[n * BIN_R + r] = 0; continue; }
+        if (!sat) {
+            c = c * (unsigned __int128)(n - r + 1) / (unsigned __int128)r;
+            if (c > (unsigned __int128)UINT64_MAX) sat = true;
+        }
+        g_binom[n * BIN_R + r] = sat ? UINT64_MAX : (uint64_t)c;
+    }
+}
+
+namespace {
+
+// C(n, r) or UINT64_MAX if it does not fit 64 bits
+__device__ uint64_t binom(int n, int r) {
+    if (r < 0 || r > n) return 0;
+    if (r > n - r) r = n - r;
+    if (n < BIN_N && r < BIN_R) return g_binom[n * BIN_R + r];
+    unsigned __int128 c = 1;
+    for (int j = 1; j <= r; ++j) {
+        c = c * (unsigned __int128)(n - r + j) / (unsigned __int128)j;
+        if (c > (unsigned __int128)UINT64_MAX) return UINT64_MAX;
+    }
+    return (uint64_t)c;
+}
+
+__device__ __forceinline__ uint64_t mul_sat(uint64_t a, uint64_t b) {
+    if (a == 0 || b == 0) return 0;
+    if (a == UINT64_MAX || b == UINT64_MAX) return UINT64_MAX;
+    return __umul64hi(a, b) ? UINT64_MAX : a * b;
+}
+__device__ __forceinline__ uint64_t add_sat(uint64_t a, uint64_t b) {
+    const uint64_t c = a + b;
+    return (c < a || a == UINT64_MAX || b == UINT64_MAX) ? UINT64_MAX : c;
+}
+
+// l-cliques of a 2-plex with f vertices adjacent to all others and p
+// non-adjacent pairs: sum_j C(p,j) 2^j C(f, l-j)
+__device__ uint64_t twoplex_count(int f, int p, int l) {
+    uint64_t s = 0;
+    const int jmax = p < l ? p : l;
+    for (int j = 0; j <= jmax; ++j) {
+        if (l - j > f) continue;
+        uint64_t t = mul_sat(binom(p, j), binom(f, l - j));
+        t = (j >= 64) ? (t ? UINT64_MAX : 0) : mul_sat(t, 1ull << j);
+        s = add_sat(s, t);
+    }
+    return s;
+}
+
+// 128-bit accumulator; a saturated (UINT64_MAX) term marks overflow
+struct Acc {
+    uint64_t lo, hi;
+    __device__ void add(uint64_t v) {
+        const uint64_t o = lo;
+        lo += v;
+        if (lo < o) ++hi;
+        if (v == UINT64_MAX) hi |= 1ull << 62;
+    }
+};
+
+template <int W>
+struct Frame {
+    uint64_t P[W];
+    uint64_t R[W];
+    int32_t x, l, y, pad;
+};
+
+template <int W>
+struct SearchMem {
+    uint64_t rows[64 * W][W];
+    int16_t col[64 * W];
+    Frame<W> fr[LDS_FRAMES];
+};
+
+// ---------------------------------------------------------------- per-lane leaves
+// One lane counts the cliques of one child candidate set Q from LDS rows.
+
+template <int W>
+__device__ __forceinline__ uint64_t lane_edges(const SearchMem<W>& M, const uint64_t (&Q)[W]) {
+    uint32_t e2 = 0;
+#pragma unroll
+    for (int wz = 0; wz < W; ++wz) {
+        uint64_t bits = Q[wz];
+        while (bits) {
+            const int z = wz * 64 + __builtin_ctzll(bits);
+            bits &= bits - 1;
+#pragma unroll
+            for (int w = 0; w < W; ++w) e2 += popc64(Q[w] & M.rows[z][w]);
+        }
+    }
+    return e2 / 2;
+}
+
+// Triangles inside Q.  Degrees first; dense Q (missing pairs M <= edges E):
+// T = C(q,3) - M(q-2) + sum_v C(m_v,2) - T_c with m_v the missing pairs at v
+// and T_c the triangles of missing pairs; sparse Q: common out-neighbours
+// along the DAG edges.
+template <int W>
+__device__ __forceinline__ uint64_t lane_triangles(const SearchMem<W>& M, const uint64_t (&Q)[W], uint64_t& ops) {
+    const int q = popcW(Q);
+    if (q < 3) return 0;
+    uint32_t e2 = 0, s2 = 0;
+#pragma unroll
+    for (int wz = 0; wz < W; ++wz) {
+        uint64_t bits = Q[wz];
+        while (bits) {
+            const int z = wz * 64 + __builtin_ctzll(bits);
+            bits &= bits - 1;
+            int d = 0;
+#pragma unroll
+            for (int w = 0; w < W; ++w) d += popc64(Q[w] & M.rows[z][w]);
+            e2 += d;
+            const int cm = q - 1 - d;
+            s2 += (uint32_t)(cm * (cm - 1) / 2);
+        }
+    }
+    const uint64_t q64 = (uint64_t)q;
+    const uint64_t Mp = (q64 * (q64 - 1) - e2) / 2, E = e2 / 2;
+    const uint64_t C3 = q64 * (q64 - 1) * (q64 - 2) / 6;
+    ops += (uint64_t)q * W;
+    if (Mp == 0) return C3;
+    const bool dense = Mp <= E;
+    ops += (dense ? Mp : E) * W;
+    uint32_t t = 0;
+#pragma unroll
+    for (int wz = 0; wz < W; ++wz) {
+        uint64_t bits = Q[wz];
+        while (bits) {
+            const int z = wz * 64 + __builtin_ctzll(bits);
+            bits &= bits - 1;
+            uint64_t Cz[W];  // missing (dense) or present (sparse) pairs z-y, y > z, inside Q
+#pragma unroll
+            for (int w = 0; w < W; ++w) {
+                const uint64_t row = dense ? ~M.rows[z][w] : M.rows[z][w];
+                Cz[w] = Q[w] & row & upper_mask(z, w);
+            }
+#pragma unroll
+            for (int wy = 0; wy < W; ++wy) {
+                while (Cz[wy]) {
+                    const int y = wy * 64 + __builtin_ctzll(Cz[wy]);
+                    Cz[wy] &= Cz[wy] - 1;
+#pragma unroll
+                    for (int w = 0; w < W; ++w) {
+                        const uint64_t row = dense ? ~M.rows[y][w] : M.rows[y][w];
+                        if (w >= wy) t += popc64(Cz[w] & row);
+                    }
+                }
+            }
+        }
+    }
+    return dense ? C3 - Mp * (q64 - 2) + s2 - t : (uint64_t)t;
+}
+
+}  // namespace
+
+template <int W, bool LIST>
+__global__ __launch_bounds__(256) void k_search(SearchArgs a) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    SearchMem<W>& M = reinterpret_cast<SearchMem<W>*>(smem_raw)[threadIdx.x / 64];
+    Frame<W>* gfr = a.gframes ? reinterpret_cast<Frame<W>*>(a.gframes) +
+                                    ((int64_t)blockIdx.x * 4 + threadIdx.x / 64) * GLOBAL_FRAMES
+                              : nullptr;
+    // frames past the LDS ones live in this wave's slab of device memory;
+    // every lane writes them (identical values) and reads back its own stores
+    auto FR = [&](int d) -> Frame<W>& { return d < LDS_FRAMES ? M.fr[d] : gfr[d - LDS_FRAMES]; };
+    const int lane = lane_id();
+    const int k = a.k, opts = a.opts;
+    const bool rule1 = opts & OPT_RULE1, rule2 = opts & OPT_RULE2, et = opts & OPT_ET, t2 = opts & OPT_TPLEX2;
+    const bool work = opts & OPT_WORK;
+    Acc acc{0, 0};
+    uint64_t wk_tasks = 0, wk_nodes = 0, wk_ops = 0;
+
+    for (;;) {
+        unsigned long long it = 0;
+        if (lane == 0) it = atomicAdd(a.next, 1ull);
+        it = uni64(__shfl(it, 0, 64));
+        if ((int64_t)it >= a.ntasks) break;
+        const int64_t task = a.tasks[it];
+        const int64_t slot = task_slot(task);
+        const int x0 = task_x0(task), x1 = task_x1(task);
+        const int c = uniform_i32(a.A.seed_c[slot]);
+        const int64_t ro = a.A.row_off[slot], vo = a.A.vtx_off[slot];
+        wk_tasks += work;
+
+        // ---- load the sub-branch into LDS (coalesced)
+        for (int i = lane; i < c * W; i += 64) (&M.rows[0][0])[i] = a.A.rows[ro + i];
+        for (int i = lane; i < c; i += 64) M.col[i] = a.A.col[vo + i];
+        wave_sync();
+        // lane-owned symmetric rows; colour class lane + 64 q (colour lane + 64 q + 1)
+        // occupies relabelled positions [#(col > colour), #(col >= colour))
+        uint64_t srow[W][W], cls[W][W];
+        const int ncol = uniform_i32(M.col[0]);
+#pragma unroll
+        for (int q = 0; q < W; ++q) {
+            const int x = lane + 64 * q;
+#pragma unroll
+            for (int w = 0; w < W; ++w) srow[q][w] = x < c ? M.rows[x][w] : 0;
+            const int cv = x + 1;
+            int lo = 0, hi = c;
+            while (lo < hi) { int mid = (lo + hi) >> 1; if (M.col[mid] > cv) lo = mid + 1; else hi = mid; }
+            const int s0 = lo;
+            hi = c;
+            while (lo < hi) { int mid = (lo + hi) >> 1; if (M.col[mid] >= cv) lo = mid + 1; else hi = mid; }
+            const int s1 = cv <= ncol ? lo : s0;
+#pragma unroll
+            for (int w = 0; w < W; ++w) {
+                const int a0 = s0 > 64 * w ? s0 : 64 * w, a1 = s1 < 64 * w + 64 ? s1 : 64 * w + 64;
+                uint64_t mk = 0;
+                if (a1 > a0) {
+                    const int len = a1 - a0;
+                    mk = (len == 64 ? ~0ull : ((1ull << len) - 1)) << (a0 - 64 * w);
+                }
+                cls[q][w] = mk;
+            }
+        }
+        Acc tacc{0, 0};
+
+        // Count a node that needs no branching: returns true and sets val, or
+        // false when the node (l >= 4) must be branched on.
+        auto finish = [&](const uint64_t (&P)[W], int l, uint64_t& val) -> bool {
+            const int pc = popcW(P);
+            val = 0;
+            if (work) { wk_nodes += 1; wk_ops += W; }
+            if (pc < l) return true;
+            if (l == 1) { val = (uint64_t)pc; return true; }
+            int mn = 1 << 30, nf = 0;
+            uint32_t dsum = 0, s2 = 0;
+#pragma unroll
+            for (int q = 0; q < W; ++q) {
+                if ((P[q] >> lane) & 1) {
+                    int d = 0;
+#pragma unroll
+                    for (int w = 0; w < W; ++w) d += popc64(P[w] & srow[q][w]);
+                    mn = d < mn ? d : mn;
+                    nf += (d == pc - 1);
+                    dsum += d;
+                    const int cm = pc - 1 - d;
+                    s2 += (uint32_t)(cm * (cm - 1) / 2);
+                }
+            }
+            if (work) wk_ops += (uint64_t)pc * W;
+            const uint64_t twoE = wave_sum(dsum);
+            if (l == 2) { val = twoE / 2; return true; }
+            if (et) {
+                const int mind = wave_min(mn);
+                if (mind >= pc - 1) { val = binom(pc, l); return true; }
+                if (t2 && mind >= pc - 2) {
+                    const int nfull = wave_sum(nf);
+                    val = twoplex_count(nfull, (pc - nfull) / 2, l);
+                    return true;
+                }
+            }
+            if (l != 3) return false;
+            // triangles inside P: dense -> missing-pair identity, sparse -> DAG edges
+            const uint64_t p64 = (uint64_t)pc;
+            const uint64_t Mp = (p64 * (p64 - 1) - twoE) / 2;
+            uint32_t t = 0;
+            const bool dense = Mp <= twoE / 2;
+#pragma unroll
+            for (int q = 0; q < W; ++q) {
+                const int z = lane + 64 * q;
+                if ((P[q] >> lane) & 1) {
+                    uint64_t Cz[W];
+#pragma unroll
+                    for (int w = 0; w < W; ++w)
+                        Cz[w] = P[w] & (dense ? ~srow[q][w] : srow[q][w]) & upper_mask(z, w);
+#pragma unroll
+                    for (int wy = 0; wy < W; ++wy) {
+                        while (Cz[wy]) {
+                            const int y = wy * 64 + __builtin_ctzll(Cz[wy]);
+                            Cz[wy] &= Cz[wy] - 1;
+#pragma unroll
+                            for (int w = 0; w < W; ++w) {
+                                const uint64_t row = dense ? ~M.rows[y][w] : M.rows[y][w];
+                                if (w >= wy) t += popc64(Cz[w] & row);
+                            }
+                        }
+                    }
+                }
+            }
+            if (work) wk_ops += (dense ? Mp : twoE / 2) * W;
+            const uint64_t T = wave_sum(t);
+            if (dense) {
+                const uint64_t S2 = wave_sum(s2);
+                val = p64 * (p64 - 1) * (p64 - 2) / 6 - Mp * (p64 - 2) + S2 - T;
+            } else {
+                val = T;
+            }
+            return true;
+        };
+
+        // children of a node with l = 5 (l = 4), x in [xlo, xhi), counted by
+        // lanes: lane j of chunk q takes y = 64 q + j
+        auto children_by_lanes = [&](const uint64_t (&P)[W], int l, int xlo, int xhi) {
+            uint64_t lsum = 0, lops = 0;
+            const int lc = l - 2;
+            int xx = xlo - 1;
+            while (true) {
+                int nx = -1;
+#pragma unroll
+                for (int w = W - 1; w >= 0; --w) {
+                    const uint64_t b = P[w] & (xx < 0 ? ~0ull : upper_mask(xx, w));
+                    if (b) nx = w * 64 + __builtin_ctzll(b);
+                }
+                if (nx < 0 || nx >= xhi || (rule1 && M.col[nx] < l)) break;
+                xx = nx;
+                uint64_t Rx[W];
+#pragma unroll
+                for (int w = 0; w < W; ++w) Rx[w] = P[w] & M.rows[xx][w] & upper_mask(xx, w);
+                const int rc = popcW(Rx);
+                if (rc < lc + 1) continue;
+                if (work) { wk_nodes += rc; wk_ops += (uint64_t)rc * W; }
+#pragma unroll
+                for (int q = 0; q < W; ++q) {
+                    if (Rx[q] == 0) continue;
+                    const int y = 64 * q + lane;
+                    const bool act = ((Rx[q] >> lane) & 1) && !(rule1 && M.col[y] < l - 1);
+                    if (act) {
+                        uint64_t Q[W];
+#pragma unroll
+                        for (int w = 0; w < W; ++w) Q[w] = Rx[w] & M.rows[y][w] & upper_mask(y, w);
+                        if (lc == 3) lsum += lane_triangles(M, Q, lops);
+                        else lsum += lane_edges(M, Q);
+                    }
+                }
+            }
+            if (work) wk_ops += wave_sum(lops);
+            tacc.add(wave_sum(lsum));
+        };
+
+        const int l0 = k - 2;
+        uint64_t P0[W];
+        prefix_mask<W>(c, P0);
+        uint64_t rootval = 0;
+        bool active = !finish(P0, l0, rootval);
+        if (!active && x0 == 0) tacc.add(rootval);  // a split seed adds its closed form once
+        if (active && (l0 == 4 || l0 == 5)) {
+            children_by_lanes(P0, l0, x0, x1);
+            active = false;
+        }
+        // depth-first search: the node being branched on lives in registers
+        // (P, R, x, l); its ancestors are frames
+        int sp = 0;
+        uint64_t P[W], R[W];
+        int x = x0 - 1, l = l0;
+#pragma unroll
+        for (int w = 0; w < W; ++w) { P[w] = P0[w]; R[w] = 0; }
+        while (active) {
+            int y = -1;
+            while (true) {
+                bool any = false;
+#pragma unroll
+                for (int w = 0; w < W; ++w) any |= R[w] != 0;
+                if (any) {
+                    int wy = 0;
+#pragma unroll
+                    for (int w = W - 1; w >= 0; --w) if (R[w]) wy = w;
+                    y = wy * 64 + __builtin_ctzll(R[wy]);
+#pragma unroll
+                    for (int w = 0; w < W; ++w) if (w == wy) R[w] &= R[w] - 1;
+                    if (rule1 && M.col[y] < l - 1) {
+#pragma unroll
+                        for (int w = 0; w < W; ++w) R[w] = 0;
+                        continue;
+                    }
+                    break;
+                }
+                int nx = -1;
+#pragma unroll
+                for (int w = W - 1; w >= 0; --w) {
+                    const uint64_t b = P[w] & (x < 0 ? ~0ull : upper_mask(x, w));
+                    if (b) nx = w * 64 + __builtin_ctzll(b);
+                }
+                const int xlim = sp == 0 ? x1 : c;
+                if (nx < 0 || nx >= xlim || (rule1 && M.col[nx] < l)) { y = -1; break; }
+                x = nx;
+#pragma unroll
+                for (int w = 0; w < W; ++w) R[w] = P[w] & M.rows[x][w] & upper_mask(x, w);
+            }
+            if (y < 0) {  // node exhausted: resume the parent
+                if (sp == 0) break;
+                --sp;
+                Frame<W>& F = FR(sp);
+#pragma unroll
+                for (int w = 0; w < W; ++w) { P[w] = uni64(F.P[w]); R[w] = uni64(F.R[w]); }
+                x = uniform_i32(F.x);
+                l = uniform_i32(F.l);
+                continue;
+            }
+            uint64_t Pc[W];
+#pragma unroll
+            for (int w = 0; w < W; ++w) Pc[w] = R[w] & M.rows[y][w] & upper_mask(y, w);
+            const int lc = l - 2;
+            if (work) wk_ops += W;
+            if (popcW(Pc) < lc) continue;
+            if (rule2 && lc >= 3) {
+                if (work) wk_ops += W;
+                int dc = 0;
+#pragma unroll
+                for (int q = 0; q < W; ++q) {
+                    uint64_t hit = 0;
+#pragma unroll
+                    for (int w = 0; w < W; ++w) hit |= Pc[w] & cls[q][w];
+                    dc += popc64(ballot(hit != 0));
+                }
+                if (dc < lc) continue;
+            }
+            uint64_t v = 0;
+            if (finish(Pc, lc, v)) { tacc.add(v); continue; }
+            if (lc == 4 || lc == 5) { children_by_lanes(Pc, lc, 0, c); continue; }
+            if (sp >= LDS_FRAMES + (gfr ? GLOBAL_FRAMES : 0)) {
+                if (lane == 0) atomicOr(a.err, ERR_DEPTH);
+                continue;
+            }
+            if (lane == 0 || sp >= LDS_FRAMES) {
+                Frame<W>& F = FR(sp);
+#pragma unroll
+                for (int w = 0; w < W; ++w) { F.P[w] = P[w]; F.R[w] = R[w]; }
+                F.x = x;
+                F.l = l;
+                F.y = y;
+            }
+            ++sp;
+            wave_sync();
+#pragma unroll
+            for (int w = 0; w < W; ++w) { P[w] = Pc[w]; R[w] = 0; }
+            x = -1;
+            l = lc;
+        }
+
+        if (tacc.hi && lane == 0) atomicOr(a.err, ERR_OVERFLOW);
+        if (a.per_task && lane == 0) a.per_task[it] = tacc.lo;
+        const uint64_t o = acc.lo;
+        acc.lo += tacc.lo;
+        if (acc.lo < o) ++acc.hi;
+        acc.hi += tacc.hi;
+        wave_sync();
+    }
+    if (work && lane == 0) {
+        atomicAdd(&a.work[0], (unsigned long long)wk_tasks);
+        atomicAdd(&a.work[1], (unsigned long long)wk_nodes);
+        atomicAdd(&a.work[2], (unsigned long long)wk_ops);
+    }
+    if (lane == 0 && (acc.lo || acc.hi)) {
+        const unsigned long long old = atomicAdd(&a.total[0], (unsigned long long)acc.lo);
+        const unsigned long long carry = (old + acc.lo < old) ? 1ull : 0ull;
+        if (acc.hi + carry) atomicAdd(&a.total[1], (unsigned long long)(acc.hi + carry));
+    }
+}
+
+namespace {
+
+template <int W, bool LIST>
+int64_t grid_blocks(int64_t ntasks, int cus, int blocks_per_cu) {
+    auto kern = k_search<W, LIST>;
+    const size_t smem = 4 * sizeof(SearchMem<W>);
+    if (hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem) != hipSuccess)
+        return -1;
+    int occ = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, 256, smem) != hipSuccess) return -1;
+    if (occ < 1) occ = 1;
+    if (blocks_per_cu > 0 && blocks_per_cu < occ) occ = blocks_per_cu;
+    int64_t grid = (int64_t)occ * cus;
+    const int64_t need = (ntasks + 3) / 4;
+    if (grid > need) grid = need;
+    if (grid < 1) grid = 1;
+    return grid;
+}
+
+template <int W, bool LIST>
+hipError_t launch_w(const SearchArgs& a, int cus, int bpc, hipStream_t s) {
+    const int64_t grid = grid_blocks<W, LIST>(a.ntasks, cus, bpc);
+    if (grid < 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_search<W, LIST>), dim3((unsigned)grid), dim3(256), 4 * sizeof(SearchMem<W>), s, a);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_search(int W, bool list, const SearchArgs& a, int cus, int bpc, hipStream_t s) {
+    if (a.ntasks <= 0) return hipSuccess;
+    if (list) return hipErrorInvalidValue;
+    switch (W) {
+        case 1: return launch_w<1, false>(a, cus, bpc, s);
+        case 2: return launch_w<2, false>(a, cus, bpc, s);
+        case 3: return launch_w<3, false>(a, cus, bpc, s);
+        case 4: return launch_w<4, false>(a, cus, bpc, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+int64_t search_grid_waves(int W, bool list, int64_t ntasks, int cus, int bpc) {
+    (void)list;
+    int64_t b = -1;
+    switch (W) {
+        case 1: b = grid_blocks<1, false>(ntasks, cus, bpc); break;
+        case 2: b = grid_blocks<2, false>(ntasks, cus, bpc); break;
+        case 3: b = grid_blocks<3, false>(ntasks, cus, bpc); break;
+        case 4: b = grid_blocks<4, false>(ntasks, cus, bpc); break;
+    }
+    return b < 0 ? -1 : 4 * b;
+}
+
+size_t search_frame_bytes(int W) {
+    switch (W) {
+        case 1: return sizeof(Frame<1>);
+        case 2: return sizeof(Frame<2>);
+        case 3: return sizeof(Frame<3>);
+        case 4: return sizeof(Frame<4>);
+    }
+    return 0;
+}
+
+hipError_t launch_binom_init(hipStream_t s) {
+    hipLaunchKernelGGL(k_binom_init, dim3((BIN_N + 255) / 256), dim3(256), 0, s);
+    return hipGetLastError();
+}
+
+}  // namespace ebb
