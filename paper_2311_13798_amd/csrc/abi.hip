@@ -91,15 +91,18 @@ ebbkc_status ebbkc_count_range(ebbkc_graph* g, int32_t k, int64_t r_begin, int64
 
 ebbkc_status ebbkc_count_seeds(ebbkc_graph* g, int32_t k, const int64_t* eids, int64_t ne, int32_t ptr_kind,
                                uint64_t* out, void* stream) {
-    (void)g; (void)k; (void)eids; (void)ne; (void)ptr_kind; (void)out; (void)stream;
-    return EBBKC_E_INVALID_ARG;
+    if (!g || (ne > 0 && (!eids || !out)) || ne < 0) return EBBKC_E_INVALID_ARG;
+    return ebb::count_seeds_impl(g, k, eids, ne, ptr_kind, out, (hipStream_t)stream);
 }
 
 ebbkc_status ebbkc_list(ebbkc_graph* g, int32_t k, int64_t r_begin, int64_t r_end, int32_t* d_buf, uint64_t cap,
                         uint32_t flags, uint64_t* out_written, uint64_t* out_checksums, void* stream) {
-    (void)g; (void)k; (void)r_begin; (void)r_end; (void)d_buf; (void)cap; (void)flags; (void)out_written;
-    (void)out_checksums; (void)stream;
-    return EBBKC_E_INVALID_ARG;
+    if (!g || !out_written || (cap > 0 && !d_buf)) return EBBKC_E_INVALID_ARG;
+    uint64_t written = 0;
+    ebbkc_status st = ebb::list_impl(g, k, r_begin, r_end, d_buf, cap, flags, &written, out_checksums,
+                                     (hipStream_t)stream);
+    if (st == EBBKC_OK || st == EBBKC_E_BUFFER_TOO_SMALL) *out_written = written;
+    return st;
 }
 
 ebbkc_status ebbkc_export(const ebbkc_graph* gc, int32_t which, int32_t* dst, int32_t ptr_kind, void* stream) {

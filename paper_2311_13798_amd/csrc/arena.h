@@ -28,7 +28,7 @@ struct GraphView {
     const int32_t* rank;
 };
 
-// Seeds are the edges with |V(g_i)| >= 2 in rank order; slot s of the arena
+// Seeds are the edges with |V(g_i)| >= 1 in rank order; slot s of the arena
 // holds seed s.
 struct ArenaView {
     const int32_t* seed_eid;  // edge id of slot s
@@ -89,6 +89,15 @@ hipError_t launch_search(int W, bool list, const SearchArgs& a, int cus, int blo
 int64_t search_grid_waves(int W, bool list, int64_t ntasks, int cus, int blocks_per_cu);
 size_t search_frame_bytes(int W);
 hipError_t launch_binom_init(hipStream_t s);
+hipError_t launch_list(int W, const SearchArgs& a, int cus, hipStream_t s);
+size_t list_frame_bytes(int W);
+int64_t list_grid_waves(int W, int64_t ntasks, int cus);
+hipError_t canon_tuples(int32_t* buf, int64_t n, int k, hipStream_t s);
+hipError_t sort_tuples(int32_t* buf, int64_t n, int k, int bits, uint64_t* keys, uint64_t* keys2, uint32_t* idx,
+                       uint32_t* idx2, int64_t* hist, int64_t* htmp, int32_t* tmpbuf, hipStream_t s);
+hipError_t tuple_checksums(const int32_t* buf, int64_t n, int k, unsigned long long* d_out, hipStream_t s);
+hipError_t list_small(const int32_t* byrank, const int32_t* eu, const int32_t* ev, int64_t lo, int64_t hi, int k,
+                      int32_t* out, hipStream_t s);
 hipError_t launch_subsize(const GraphView& G, int64_t m, int32_t* out, hipStream_t s);
 
 }  // namespace ebb

@@ -4,7 +4,7 @@
 // Seeds.  Every k-clique is counted under the edge of the clique that comes
 // first in pi_tau (Section 4.1), inside that edge's sub-branch g_i, which
 // needs at least k-2 vertices.  The arena keeps g_i for every edge with
-// |V(g_i)| >= 2, in rank order, so a rank range is a slot range.
+// |V(g_i)| >= 1, in rank order, so a rank range is a slot range.
 //
 // Tasks.  For a count at k, every slot with |V(g_i)| >= k-2 becomes one task;
 // a slot whose root has more than split_threshold (k-2)-subsets becomes one
@@ -68,7 +68,7 @@ inline unsigned grid_for(int64_t n, int per = 256) {
 __global__ void k_seed_flags(const int32_t* __restrict__ byrank, const int32_t* __restrict__ subsize, int64_t m,
                              int32_t* __restrict__ flag) {
     for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < m; r += (int64_t)gridDim.x * blockDim.x)
-        flag[r] = subsize[byrank[r]] >= 2;
+        flag[r] = subsize[byrank[r]] >= 1;
 }
 
 __global__ void k_seed_fill(const int32_t* __restrict__ byrank, const int32_t* __restrict__ subsize,
@@ -391,6 +391,52 @@ static size_t task_bytes(int64_t n, int64_t T) {
            rnd256((size_t)(scan_tmp_elems(hn) + 64) * 8) + 4096;
 }
 
+// One search launch per width class over a sorted task list (classes are
+// contiguous).  list = false: counts (per_task optional); list = true: tuples.
+static ebbkc_status run_tasks(ebbkc_graph* g, int32_t k, const int64_t* tsorted, const uint64_t ccount[4],
+                              uint64_t* per_task, const uint64_t* task_off, int32_t* out, void* gframes, bool list,
+                              hipStream_t s) {
+    hipEvent_t ev[MAX_W + 1][2] = {};
+    int64_t off = 0;
+    for (int W = 1; W <= MAX_W; ++W) {
+        const int64_t nt = (int64_t)ccount[W - 1];
+        if (!nt) continue;
+        CHKH(hipEventCreate(&ev[W][0]));
+        CHKH(hipEventCreate(&ev[W][1]));
+        SearchArgs a{};
+        a.A = ArenaView{g->seed_eid, g->seed_c, g->row_off, g->vtx_off, g->arows, g->agid, g->acol};
+        a.tasks = tsorted + off;
+        a.ntasks = nt;
+        a.k = k;
+        a.opts = opts_of(g->opt);
+        a.next = (unsigned long long*)(g->d_counters + W - 1);
+        a.total = (unsigned long long*)(g->d_counters + 4);
+        a.work = (unsigned long long*)(g->d_counters + 8);
+        a.err = (int*)(g->d_counters + 6);
+        a.per_task = per_task ? per_task + off : nullptr;
+        a.task_off = task_off ? task_off + off : nullptr;
+        a.out = out;
+        a.eu = g->eu;
+        a.ev = g->ev;
+        a.gframes = gframes;
+        CHKH(hipMemsetAsync(a.next, 0, sizeof(uint64_t), s));
+        CHKH(hipEventRecord(ev[W][0], s));
+        if (list) CHKH(launch_list(W, a, g->cu_count, s));
+        else CHKH(launch_search(W, false, a, g->cu_count, g->opt.blocks_per_cu, s));
+        CHKH(hipEventRecord(ev[W][1], s));
+        off += nt;
+    }
+    CHKH(hipStreamSynchronize(s));
+    for (int W = 1; W <= MAX_W; ++W) {
+        if (!ev[W][0]) continue;
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, ev[W][0], ev[W][1]) == hipSuccess && !list) g->last_ms[W - 1] = ms;
+        (void)hipEventDestroy(ev[W][0]);
+        (void)hipEventDestroy(ev[W][1]);
+    }
+    return EBBKC_OK;
+}
+
 ebbkc_status count_impl(ebbkc_graph* g, int32_t k, int64_t r_begin, int64_t r_end, const int64_t* d_eids, int64_t ne,
                         uint64_t* d_per_seed, uint64_t* out, hipStream_t s) {
     (void)d_eids;
@@ -466,39 +512,202 @@ ebbkc_status count_impl(ebbkc_graph* g, int32_t k, int64_t r_begin, int64_t r_en
     void* gframes = deep ? (void*)cv.take<char>((int64_t)fbytes) : nullptr;
     if (deep && !gframes) return EBBKC_E_OOM;
 
-    // ---- search, one launch per width class (classes are contiguous in tsorted)
-    hipEvent_t ev[MAX_W + 1][2] = {};
-    int64_t off = 0;
-    for (int W = 1; W <= MAX_W; ++W) {
-        const int64_t nt = (int64_t)ccount[W - 1];
-        if (!nt) continue;
-        CHKH(hipEventCreate(&ev[W][0]));
-        CHKH(hipEventCreate(&ev[W][1]));
-        SearchArgs a{};
-        a.A = ArenaView{g->seed_eid, g->seed_c, g->row_off, g->vtx_off, g->arows, g->agid, g->acol};
-        a.tasks = tsorted + off;
-        a.ntasks = nt;
-        a.k = k;
-        a.opts = opts_of(g->opt);
-        a.next = (unsigned long long*)(g->d_counters + W - 1);
-        a.total = total;
-        a.work = (unsigned long long*)(g->d_counters + 8);
-        a.err = (int*)(g->d_counters + 6);
-        a.gframes = gframes;
-        CHKH(hipEventRecord(ev[W][0], s));
-        CHKH(launch_search(W, false, a, g->cu_count, g->opt.blocks_per_cu, s));
-        CHKH(hipEventRecord(ev[W][1], s));
-        off += nt;
+    // ---- search, one launch per width class
+    st = run_tasks(g, k, tsorted, ccount, nullptr, nullptr, nullptr, gframes, false, s);
+    if (st) return st;
+    return read_total(g, out, s);
+}
+
+static int bits_for(uint64_t x) {
+    int b = 0;
+    while (b < 64 && (x >> b)) ++b;
+    return b;
+}
+
+ebbkc_status list_impl(ebbkc_graph* g, int32_t k, int64_t r_begin, int64_t r_end, int32_t* d_buf, uint64_t cap,
+                       uint32_t flags, uint64_t* out_written, uint64_t* out_checksums, hipStream_t s) {
+    if (k < 1 || k > 64) return EBBKC_E_K_RANGE;
+    ebbkc_status st = ensure_counters(g);
+    if (st) return st;
+    if (ensure_binom(g->device, s) != hipSuccess) return EBBKC_E_HIP;
+    if (r_end < 0 || r_end > g->m) r_end = g->m;
+    if (r_begin < 0 || r_begin > r_end) return EBBKC_E_INVALID_ARG;
+    uint64_t N = 0;
+    void* tmp_sort = nullptr;
+    struct FreeOnExit { void*& p; ~FreeOnExit() { if (p) (void)hipFree(p); } } fe{tmp_sort};
+    if (k <= 2) {
+        if (k == 1 && (r_begin != 0 || r_end != g->m)) return EBBKC_E_INVALID_ARG;
+        N = k == 1 ? (uint64_t)g->n : (uint64_t)(r_end - r_begin);
+        *out_written = N;
+        if (N > cap) return EBBKC_E_BUFFER_TOO_SMALL;
+        if (N) CHKH(list_small(g->byrank, g->eu, g->ev, k == 1 ? 0 : r_begin, k == 1 ? g->n : r_end, k, d_buf, s));
+    } else {
+        st = arena_impl(g, s);
+        if (st) return st;
+        CHKH(hipMemsetAsync(g->d_counters, 0, CNT_WORDS * sizeof(uint64_t), s));
+        const auto& SR = g->seed_rank_host;
+        const int64_t i0 =
+            std::lower_bound(SR.begin(), SR.end(), (int32_t)std::min<int64_t>(r_begin, INT32_MAX)) - SR.begin();
+        const int64_t i1 =
+            std::lower_bound(SR.begin(), SR.end(), (int32_t)std::min<int64_t>(r_end, INT32_MAX)) - SR.begin();
+        const int64_t n = i1 - i0;
+        if (n > 0) {
+            const int l0 = k - 2;
+            const double thr = g->opt.split_threshold > 0 ? (double)g->opt.split_threshold : (double)(1 << 22);
+            const double log_thr = g->opt.split_threshold < 0 ? 1e300 : std::log(thr);
+            Carve cv0{(char*)scratch_get(g, task_bytes(n, 1)), 0, 0};
+            cv0.cap = g->scratch_bytes;
+            int32_t* tcount = cv0.take<int32_t>(n);
+            int64_t* toff = cv0.take<int64_t>(n + 1);
+            int64_t* tmp = cv0.take<int64_t>(scan_tmp_elems(n + 1) + 64);
+            if (!tcount || !toff || !tmp) return EBBKC_E_OOM;
+            hipLaunchKernelGGL(k_task_counts, dim3(grid_for(n)), dim3(256), 0, s, g->seed_c, i0, n, l0, log_thr,
+                               tcount);
+            CHKH(exclusive_scan_i32(tcount, toff, n, toff + n, tmp, s));
+            int64_t T = 0;
+            CHKH(hipMemcpyAsync(&T, toff + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+            CHKH(hipStreamSynchronize(s));
+            if (T > 0) {
+                const bool deep = k > 2 + 2 * 16 + 2;
+                const int64_t waves = list_grid_waves(MAX_W, T, g->cu_count);
+                const int64_t wsearch = search_grid_waves(MAX_W, false, T, g->cu_count, g->opt.blocks_per_cu);
+                const size_t fbytes = deep ? (size_t)std::max(waves, wsearch) * GLOBAL_FRAMES *
+                                                 std::max(list_frame_bytes(MAX_W), search_frame_bytes(MAX_W))
+                                           : 0;
+                const size_t need = task_bytes(n, T) + rnd256(fbytes) + 2 * rnd256((size_t)(T + 1) * 8) +
+                                    rnd256((size_t)(scan_tmp_elems(T + 1) + 64) * 8);
+                if (!scratch_get(g, need)) return EBBKC_E_OOM;
+                Carve cv{(char*)g->scratch, 0, g->scratch_bytes};
+                int64_t* tsorted = nullptr;
+                uint64_t ccount[4] = {0, 0, 0, 0};
+                int64_t T2 = 0;
+                st = make_tasks(g, i0, n, l0, log_thr, s, cv, &tsorted, &T2, ccount);
+                if (st) return st;
+                void* gframes = deep ? (void*)cv.take<char>((int64_t)fbytes) : nullptr;
+                uint64_t* per_task = cv.take<uint64_t>(T + 1);
+                uint64_t* task_off = cv.take<uint64_t>(T + 1);
+                int64_t* stmp = cv.take<int64_t>(scan_tmp_elems(T + 1) + 64);
+                if ((deep && !gframes) || !per_task || !task_off || !stmp) return EBBKC_E_OOM;
+                // pass 1: per-task counts
+                CHKH(hipMemsetAsync(g->d_counters + 4, 0, 4 * sizeof(uint64_t), s));
+                st = run_tasks(g, k, tsorted, ccount, per_task, nullptr, nullptr, gframes, false, s);
+                if (st) return st;
+                st = read_total(g, &N, s);
+                if (st) return st;
+                *out_written = N;
+                if (N > cap) return EBBKC_E_BUFFER_TOO_SMALL;
+                CHKH(exclusive_scan_i64((const int64_t*)per_task, (int64_t*)task_off, T, nullptr, stmp, s));
+                // pass 2: tuples
+                st = run_tasks(g, k, tsorted, ccount, per_task, task_off, d_buf, gframes, true, s);
+                if (st) return st;
+                uint64_t herr = 0;
+                CHKH(hipMemcpyAsync(&herr, g->d_counters + 6, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+                CHKH(hipStreamSynchronize(s));
+                if (herr & ERR_CAP) return EBBKC_E_HIP;
+                if (herr & ERR_DEPTH) return EBBKC_E_K_RANGE;
+            }
+        }
+        *out_written = N;
     }
-    st = read_total(g, out, s);
-    for (int W = 1; W <= MAX_W; ++W) {
-        if (!ev[W][0]) continue;
-        float ms = 0.f;
-        if (hipEventElapsedTime(&ms, ev[W][0], ev[W][1]) == hipSuccess) g->last_ms[W - 1] = ms;
-        (void)hipEventDestroy(ev[W][0]);
-        (void)hipEventDestroy(ev[W][1]);
+    if (N > 0) {
+        CHKH(canon_tuples(d_buf, (int64_t)N, k, s));
+        if ((flags & EBBKC_LIST_SORTED) && N > 1) {
+            const int bits = std::max(1, bits_for((uint64_t)(g->n > 0 ? g->n - 1 : 0)));
+            const int64_t hn = radix_hist_elems((int64_t)N);
+            const size_t bytes = 2 * rnd256(N * 8) + 2 * rnd256(N * 4) + rnd256((size_t)hn * 8) +
+                                 rnd256((size_t)(scan_tmp_elems(hn) + 64) * 8) + rnd256(N * (size_t)k * 4) + 4096;
+            CHKH(hipMalloc(&tmp_sort, bytes));
+            Carve cv{(char*)tmp_sort, 0, bytes};
+            uint64_t* keys = cv.take<uint64_t>((int64_t)N);
+            uint64_t* keys2 = cv.take<uint64_t>((int64_t)N);
+            uint32_t* idx = cv.take<uint32_t>((int64_t)N);
+            uint32_t* idx2 = cv.take<uint32_t>((int64_t)N);
+            int64_t* hist = cv.take<int64_t>(hn);
+            int64_t* htmp = cv.take<int64_t>(scan_tmp_elems(hn) + 64);
+            int32_t* tbuf = cv.take<int32_t>((int64_t)N * k);
+            if (!keys || !keys2 || !idx || !idx2 || !hist || !htmp || !tbuf) return EBBKC_E_OOM;
+            if (N >= ((uint64_t)1 << 32)) return EBBKC_E_INVALID_ARG;
+            CHKH(sort_tuples(d_buf, (int64_t)N, k, bits, keys, keys2, idx, idx2, hist, htmp, tbuf, s));
+        }
     }
-    return st;
+    if (out_checksums) {
+        CHKH(tuple_checksums(d_buf, (int64_t)N, k, (unsigned long long*)(g->d_counters + 12), s));
+        CHKH(hipMemcpyAsync(out_checksums, g->d_counters + 12, 2 * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+    }
+    CHKH(hipStreamSynchronize(s));
+    return EBBKC_OK;
+}
+
+// Per-seed counts for listed edge ids: one whole-root task per seed.
+ebbkc_status count_seeds_impl(ebbkc_graph* g, int32_t k, const int64_t* eids, int64_t ne, int32_t ptr_kind,
+                              uint64_t* out, hipStream_t s) {
+    if (k < 3 || k > MAX_K) return EBBKC_E_K_RANGE;
+    ebbkc_status st = ensure_counters(g);
+    if (st) return st;
+    if (ensure_binom(g->device, s) != hipSuccess) return EBBKC_E_HIP;
+    st = arena_impl(g, s);
+    if (st) return st;
+    if (ne <= 0) return EBBKC_OK;
+    std::vector<int64_t> he((size_t)ne);
+    if (ptr_kind == EBBKC_PTR_DEVICE) CHKH(hipMemcpy(he.data(), eids, sizeof(int64_t) * ne, hipMemcpyDeviceToHost));
+    else std::copy(eids, eids + ne, he.begin());
+    if (g->seed_c_host.empty() && g->nseeds) {
+        g->seed_c_host.resize((size_t)g->nseeds);
+        CHKH(hipMemcpy(g->seed_c_host.data(), g->seed_c, sizeof(int32_t) * g->nseeds, hipMemcpyDeviceToHost));
+    }
+    if (g->rank_host.empty() && g->m) {
+        g->rank_host.resize((size_t)g->m);
+        CHKH(hipMemcpy(g->rank_host.data(), g->rank, sizeof(int32_t) * g->m, hipMemcpyDeviceToHost));
+    }
+    // tasks grouped by width class; task i -> output position
+    std::vector<int64_t> tasks[MAX_W];
+    std::vector<int64_t> where[MAX_W];
+    std::vector<uint64_t> res((size_t)ne, 0);
+    const auto& SR = g->seed_rank_host;
+    for (int64_t i = 0; i < ne; ++i) {
+        const int64_t e = he[(size_t)i];
+        if (e < 0 || e >= g->m) return EBBKC_E_INVALID_ARG;
+        const int32_t r = g->rank_host[(size_t)e];
+        const int64_t slot = std::lower_bound(SR.begin(), SR.end(), r) - SR.begin();
+        if (slot >= (int64_t)SR.size() || SR[(size_t)slot] != r) continue;  // empty sub-branch
+        const int c = g->seed_c_host[(size_t)slot];
+        if (c < k - 2) continue;
+        tasks[width_of(c) - 1].push_back(task_pack(slot, 0, c));
+        where[width_of(c) - 1].push_back(i);
+    }
+    uint64_t ccount[4];
+    int64_t T = 0;
+    for (int W = 0; W < MAX_W; ++W) { ccount[W] = tasks[W].size(); T += (int64_t)tasks[W].size(); }
+    if (T) {
+        const bool deep = k > 2 + 2 * LDS_FRAMES + 4;
+        const size_t fbytes =
+            deep ? (size_t)search_grid_waves(MAX_W, false, T, g->cu_count, g->opt.blocks_per_cu) * GLOBAL_FRAMES *
+                       search_frame_bytes(MAX_W)
+                 : 0;
+        if (!scratch_get(g, rnd256(T * 8) * 2 + rnd256(fbytes) + 4096)) return EBBKC_E_OOM;
+        Carve cv{(char*)g->scratch, 0, g->scratch_bytes};
+        int64_t* dt = cv.take<int64_t>(T);
+        uint64_t* pt = cv.take<uint64_t>(T);
+        void* gframes = deep ? (void*)cv.take<char>((int64_t)fbytes) : nullptr;
+        std::vector<int64_t> flat;
+        flat.reserve((size_t)T);
+        for (int W = 0; W < MAX_W; ++W) flat.insert(flat.end(), tasks[W].begin(), tasks[W].end());
+        CHKH(hipMemcpyAsync(dt, flat.data(), sizeof(int64_t) * T, hipMemcpyHostToDevice, s));
+        CHKH(hipMemsetAsync(g->d_counters, 0, CNT_WORDS * sizeof(uint64_t), s));
+        st = run_tasks(g, k, dt, ccount, pt, nullptr, nullptr, gframes, false, s);
+        if (st) return st;
+        uint64_t tot = 0;
+        st = read_total(g, &tot, s);
+        if (st) return st;
+        std::vector<uint64_t> hp((size_t)T);
+        CHKH(hipMemcpy(hp.data(), pt, sizeof(uint64_t) * T, hipMemcpyDeviceToHost));
+        int64_t o = 0;
+        for (int W = 0; W < MAX_W; ++W)
+            for (size_t j = 0; j < where[W].size(); ++j) res[(size_t)where[W][j]] = hp[(size_t)o++];
+    }
+    if (ptr_kind == EBBKC_PTR_DEVICE) CHKH(hipMemcpy(out, res.data(), sizeof(uint64_t) * ne, hipMemcpyHostToDevice));
+    else std::copy(res.begin(), res.end(), out);
+    return EBBKC_OK;
 }
 
 }  // namespace ebb

@@ -50,6 +50,8 @@ struct ebbkc_graph {
     uint64_t* nedges = nullptr;
     int64_t arena_bytes = 0;
     std::vector<int32_t> seed_rank_host; // rank of each slot (ascending)
+    std::vector<int32_t> seed_c_host;    // |V(g_i)| of each slot (filled on demand)
+    std::vector<int32_t> rank_host;      // rank of each edge (filled on demand)
     double arena_ms = 0.0;
 
     // per-call scratch (grown on demand, freed by destroy)
@@ -71,5 +73,7 @@ ebbkc_status list_impl(ebbkc_graph* g, int32_t k, int64_t r_begin, int64_t r_end
                        uint32_t flags, uint64_t* out_written, uint64_t* out_checksums, hipStream_t s);
 ebbkc_status subsize_impl(ebbkc_graph* g, hipStream_t s);
 ebbkc_status arena_impl(ebbkc_graph* g, hipStream_t s);
+ebbkc_status count_seeds_impl(ebbkc_graph* g, int32_t k, const int64_t* eids, int64_t ne, int32_t ptr_kind,
+                              uint64_t* out, hipStream_t s);
 void* scratch_get(ebbkc_graph* g, size_t bytes);
 }  // namespace ebb

@@ -365,9 +365,16 @@ __global__ __launch_bounds__(256) void k_search(SearchArgs a) {
         const int l0 = k - 2;
         uint64_t P0[W];
         prefix_mask<W>(c, P0);
-        uint64_t rootval = 0;
-        bool active = !finish(P0, l0, rootval);
-        if (!active && x0 == 0) tacc.add(rootval);  // a split seed adds its closed form once
+        // A task covering the whole root may finish it in closed form; a
+        // task holding only the root children with x in [x0, x1) counts
+        // exactly the cliques of that part (so tasks can be listed alone).
+        const bool whole = x0 == 0 && x1 >= c;
+        bool active = true;
+        if (whole) {
+            uint64_t rootval = 0;
+            active = !finish(P0, l0, rootval);
+            if (!active) tacc.add(rootval);
+        }
         if (active && (l0 == 4 || l0 == 5)) {
             children_by_lanes(P0, l0, x0, x1);
             active = false;
