@@ -163,6 +163,39 @@ ebbkc_status ebbkc_last_work(const ebbkc_graph *g, uint64_t out[4]);
 
 void ebbkc_destroy(ebbkc_graph *g);
 
+/* ---- Batched form: many (graph, k) counts in one fused launch.
+ * The tasks of every graph of the batch (one per seed sub-branch with at
+ * least k-2 vertices; heavy roots split per first vertex) are merged into one
+ * list sorted by bitmap width and by the vertices each task can still use,
+ * and run by one persistent launch per width class, so the waves draw work
+ * from all graphs at once (root sub-branches are independent, Section 6.2
+ * (7)).  Counts are exact per graph. */
+typedef struct ebbkc_batch ebbkc_batch;
+
+/* graphs: n prepared handles on the current device (they must outlive the
+ * batch and must not be used concurrently); ks: k per graph (k >= 1).  Builds
+ * any missing sub-branch arenas and the merged task list.  opt may be NULL:
+ * then a tuning choice cached for this batch shape is used if present. */
+ebbkc_status ebbkc_batch_create(ebbkc_graph *const *graphs, const int32_t *ks, int32_t n,
+                                const ebbkc_options *opt, void *stream, ebbkc_batch **out);
+
+/* Run the batch and write the exact count of graph i to out_counts[i] (may be
+ * NULL).  use_graph = 1 replays a HIP graph captured on the first call (the
+ * counter reset, the per-class launches and the result copy); 0 launches the
+ * same sequence directly.  Synchronises stream. */
+ebbkc_status ebbkc_batch_run(ebbkc_batch *b, int32_t use_graph, uint64_t *out_counts, void *stream);
+
+/* Autotuner: times the batch under split thresholds {2^16, 2^22, 2^28, never}
+ * x workgroups per CU {auto, 1, 2}, checks every setting gives the same
+ * counts, keeps the fastest (also in the process cache and, if the
+ * environment names one, the EBBKC_TUNE_CACHE file). */
+ebbkc_status ebbkc_batch_tune(ebbkc_batch *b, void *stream, int32_t *out_split, int32_t *out_blocks_per_cu);
+
+/* Number of tasks and the host wall time (ms) of the last run. */
+ebbkc_status ebbkc_batch_info(const ebbkc_batch *b, int64_t *out_tasks, double *out_last_ms);
+
+void ebbkc_batch_destroy(ebbkc_batch *b);
+
 const char *ebbkc_strerror(ebbkc_status s);
 
 #ifdef __cplusplus

@@ -43,7 +43,8 @@ class ebbkc_info(ctypes.Structure):
 
 EXPORTED = ("ebbkc_default_options", "ebbkc_prepare", "ebbkc_count", "ebbkc_count_range", "ebbkc_count_seeds",
             "ebbkc_list", "ebbkc_export", "ebbkc_info_get", "ebbkc_last_timing", "ebbkc_last_work", "ebbkc_destroy",
-            "ebbkc_strerror")
+            "ebbkc_strerror", "ebbkc_batch_create", "ebbkc_batch_run", "ebbkc_batch_tune", "ebbkc_batch_info",
+            "ebbkc_batch_destroy")
 
 _lib = None
 
@@ -71,6 +72,14 @@ def load_library(path: str = LIB_PATH):
     lib.ebbkc_last_work.argtypes = [vp, ctypes.POINTER(ctypes.c_uint64)]
     lib.ebbkc_destroy.argtypes = [vp]
     lib.ebbkc_destroy.restype = None
+    lib.ebbkc_batch_create.argtypes = [vp, vp, i32, ctypes.POINTER(ebbkc_options), vp, ctypes.POINTER(vp)]
+    lib.ebbkc_batch_run.argtypes = [vp, i32, vp, vp]
+    lib.ebbkc_batch_tune.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
+    lib.ebbkc_batch_info.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)]
+    lib.ebbkc_batch_destroy.argtypes = [vp]
+    lib.ebbkc_batch_destroy.restype = None
+    for f in ("ebbkc_batch_create", "ebbkc_batch_run", "ebbkc_batch_tune", "ebbkc_batch_info"):
+        getattr(lib, f).restype = ctypes.c_int
     lib.ebbkc_strerror.argtypes = [i32]
     lib.ebbkc_strerror.restype = ctypes.c_char_p
     for f in ("ebbkc_prepare", "ebbkc_count", "ebbkc_count_range", "ebbkc_count_seeds", "ebbkc_list",
@@ -192,6 +201,72 @@ def ebbkc_destroy(h):
 
 def ebbkc_strerror(status: int) -> str:
     return load_library().ebbkc_strerror(status).decode()
+
+
+def ebbkc_batch_create(handles, ks, options: ebbkc_options | None = None, stream=None):
+    n = len(handles)
+    arr = (ctypes.c_void_p * n)(*[h.value if isinstance(h, ctypes.c_void_p) else h for h in handles])
+    kk = (ctypes.c_int32 * n)(*ks)
+    b = ctypes.c_void_p()
+    _check(load_library().ebbkc_batch_create(arr, kk, n, ctypes.byref(options) if options else None, _stream(stream),
+                                             ctypes.byref(b)), "ebbkc_batch_create")
+    return b
+
+
+def ebbkc_batch_run(b, use_graph: bool = True, stream=None):
+    n = _batch_sizes.get(b.value, 0)
+    out = (ctypes.c_uint64 * max(n, 1))()
+    _check(load_library().ebbkc_batch_run(b, int(use_graph), out, _stream(stream)), "ebbkc_batch_run")
+    return [int(x) for x in out[:n]]
+
+
+def ebbkc_batch_tune(b, stream=None):
+    sp, bp = ctypes.c_int32(), ctypes.c_int32()
+    _check(load_library().ebbkc_batch_tune(b, _stream(stream), ctypes.byref(sp), ctypes.byref(bp)), "ebbkc_batch_tune")
+    return int(sp.value), int(bp.value)
+
+
+def ebbkc_batch_info(b):
+    t, ms = ctypes.c_int64(), ctypes.c_double()
+    _check(load_library().ebbkc_batch_info(b, ctypes.byref(t), ctypes.byref(ms)), "ebbkc_batch_info")
+    return int(t.value), float(ms.value)
+
+
+def ebbkc_batch_destroy(b):
+    _batch_sizes.pop(b.value, None)
+    load_library().ebbkc_batch_destroy(b)
+
+
+_batch_sizes: dict = {}
+
+
+class Batch:
+    """Several (prepared graph, k) counts run as one fused launch per width class."""
+
+    def __init__(self, graphs, ks, options: ebbkc_options | None = None):
+        self._graphs = list(graphs)  # keep the handles alive
+        self._b = ebbkc_batch_create([G.handle for G in self._graphs], list(ks), options)
+        _batch_sizes[self._b.value] = len(self._graphs)
+
+    def run(self, use_graph: bool = True):
+        return ebbkc_batch_run(self._b, use_graph)
+
+    def tune(self):
+        return ebbkc_batch_tune(self._b)
+
+    def info(self):
+        return ebbkc_batch_info(self._b)
+
+    def close(self):
+        if getattr(self, "_b", None):
+            ebbkc_batch_destroy(self._b)
+            self._b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 # ---------------------------------------------------------------- convenience wrapper

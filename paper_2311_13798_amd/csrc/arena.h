@@ -82,6 +82,13 @@ struct SearchArgs {
     int32_t* out;
     const int32_t* eu;
     const int32_t* ev;
+    // batches of graphs: task i belongs to graph task_graph[i], whose arena is
+    // views[g] and whose clique size is graph_k[g]; its count is added to
+    // graph_total[2g] (low word) / [2g+1] (high word)
+    const ArenaView* views;
+    const int32_t* task_graph;
+    const int32_t* graph_k;
+    unsigned long long* graph_total;
 };
 
 hipError_t launch_build(int W, const BuildArgs& a, int cus, hipStream_t s);

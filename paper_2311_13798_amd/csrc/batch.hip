@@ -1,0 +1,499 @@
+// batch.hip -- many (graph, k) counts in one fused launch per bitmap width
+// class, captured once in a HIP graph and replayed.
+//
+// Every graph of the batch is prepared and has its sub-branch arena; the
+// tasks of all graphs (as in a single count: one per seed with enough
+// vertices, heavy roots split per first vertex) are merged into one list,
+// sorted by width class and then by the vertices a task can still use,
+// largest first, so the persistent waves of one launch draw work from every
+// graph.  Each task adds its count to its own graph's exact 128-bit total.
+//
+// Autotuning: ebbkc_batch_tune times the batch under a few (split threshold,
+// workgroups per CU) settings and keeps the fastest; the choice is cached per
+// batch signature for the process (and in the file named by EBBKC_TUNE_CACHE
+// when that variable is set).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "arena.h"
+#include "common.h"
+#include "handle.h"
+#include "prims.h"
+
+struct ebbkc_batch {
+    int device = 0;
+    std::vector<ebbkc_graph*> graphs;
+    std::vector<int32_t> ks;
+    ebbkc_options opt{};
+    int cu_count = 256;
+    // device
+    ebb::ArenaView* views = nullptr;
+    int32_t* gk = nullptr;
+    int64_t* tasks = nullptr;
+    int32_t* tgraph = nullptr;
+    unsigned long long* gtot = nullptr;  // 2 per graph
+    unsigned long long* ctr = nullptr;   // [0..4) class work counters, [4..6) unused, [6] err, [8..11] work
+    void* gframes = nullptr;
+    int64_t ntasks = 0;
+    uint64_t ccount[4] = {0, 0, 0, 0};
+    int32_t kmax = 0;
+    // host results
+    unsigned long long* h_tot = nullptr;
+    unsigned long long* h_ctr = nullptr;
+    // captured launch sequence
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    bool dirty = true;  // tasks changed since capture
+    double last_ms = 0.0;
+};
+
+namespace ebb {
+namespace {
+
+#define CHKB(expr)                                                              \
+    do {                                                                        \
+        hipError_t e_ = (expr);                                                 \
+        if (e_ != hipSuccess) {                                                 \
+            (void)hipGetLastError();                                            \
+            return e_ == hipErrorOutOfMemory ? EBBKC_E_OOM : EBBKC_E_HIP;       \
+        }                                                                       \
+    } while (0)
+
+__host__ __device__ inline int width_of(int c) { return c <= 64 ? 1 : (c <= 128 ? 2 : (c <= 192 ? 3 : 4)); }
+
+inline unsigned gridn(int64_t n) {
+    int64_t b = (n + 255) / 256;
+    if (b < 1) b = 1;
+    if (b > 16384) b = 16384;
+    return (unsigned)b;
+}
+
+__device__ __forceinline__ bool split_root_b(int c, int l0, double log_threshold) {
+    if (l0 < 4 || c < l0 + 8) return false;
+    const double lc = lgamma((double)c + 1) - lgamma((double)l0 + 1) - lgamma((double)(c - l0) + 1);
+    return lc > log_threshold;
+}
+
+__global__ void k_btask_counts(const int32_t* __restrict__ seed_c, int64_t n, int l0, double log_thr,
+                               int32_t* __restrict__ tcount) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int c = seed_c[i];
+        int t = 0;
+        if (c >= l0) t = split_root_b(c, l0, log_thr) ? c - l0 + 1 : 1;
+        tcount[i] = t;
+    }
+}
+
+__global__ void k_btask_fill(const int32_t* __restrict__ seed_c, int64_t n, int l0, double log_thr,
+                             const int64_t* __restrict__ toff, int64_t base, int32_t graph, int64_t* __restrict__ tasks,
+                             int32_t* __restrict__ tgraph, uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int c = seed_c[i];
+        if (c < l0) continue;
+        const int W = width_of(c);
+        int64_t o = base + toff[i];
+        if (split_root_b(c, l0, log_thr)) {
+            for (int x = 0; x <= c - l0; ++x, ++o) {
+                tasks[o] = task_pack(i, x, x + 1);
+                tgraph[o] = graph;
+                keys[o] = ((uint64_t)(W - 1) << 8) | (uint64_t)(255 - (c - 1 - x));
+                vals[o] = (uint32_t)o;
+            }
+        } else {
+            tasks[o] = task_pack(i, 0, c);
+            tgraph[o] = graph;
+            keys[o] = ((uint64_t)(W - 1) << 8) | (uint64_t)(255 - (c > 255 ? 255 : c));
+            vals[o] = (uint32_t)o;
+        }
+    }
+}
+
+__global__ void k_bgather(const int64_t* __restrict__ tasks, const int32_t* __restrict__ tgraph,
+                          const uint32_t* __restrict__ idx, int64_t n, int64_t* __restrict__ otasks,
+                          int32_t* __restrict__ ograph) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        otasks[i] = tasks[idx[i]];
+        ograph[i] = tgraph[idx[i]];
+    }
+}
+
+__global__ void k_bclass_hist(const uint64_t* __restrict__ keys, int64_t n, unsigned long long* __restrict__ cls) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        atomicAdd(&cls[(keys[i] >> 8) & 3], 1ull);
+}
+
+// zero the counters and per-graph totals (a kernel, so the captured graph
+// holds no memset node)
+__global__ void k_bclear(unsigned long long* __restrict__ a, int64_t na, unsigned long long* __restrict__ b,
+                         int64_t nb) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < na + nb; i += (int64_t)gridDim.x * blockDim.x) {
+        if (i < na) a[i] = 0;
+        else b[i - na] = 0;
+    }
+}
+
+int opts_of(const ebbkc_options& o) {
+    int f = 0;
+    if (o.early_termination) f |= OPT_ET;
+    if (o.t_plex >= 2) f |= OPT_TPLEX2;
+    if (o.rule1) f |= OPT_RULE1;
+    if (o.rule2) f |= OPT_RULE2;
+    return f;
+}
+
+void free_tasks(ebbkc_batch* b) {
+    if (b->tasks) (void)hipFree(b->tasks);
+    if (b->tgraph) (void)hipFree(b->tgraph);
+    if (b->gframes) (void)hipFree(b->gframes);
+    b->tasks = nullptr;
+    b->tgraph = nullptr;
+    b->gframes = nullptr;
+    b->ntasks = 0;
+    b->dirty = true;
+}
+
+// Build the merged, sorted task list under the batch's current options.
+ebbkc_status build_tasks(ebbkc_batch* b, hipStream_t s) {
+    free_tasks(b);
+    const int n = (int)b->graphs.size();
+    const double thr = b->opt.split_threshold > 0 ? (double)b->opt.split_threshold : (double)(1 << 22);
+    const double log_thr = b->opt.split_threshold < 0 ? 1e300 : std::log(thr);
+    // per graph: task counts and offsets (scratch sized for the largest graph)
+    std::vector<int64_t> gbase((size_t)n + 1, 0);
+    std::vector<int64_t*> toffs((size_t)n, nullptr);
+    int64_t total = 0, nsmax = 0;
+    for (int i = 0; i < n; ++i) nsmax = std::max(nsmax, b->graphs[(size_t)i]->nseeds);
+    int32_t* tc = nullptr;
+    int64_t* tmp = nullptr;
+    CHKB(hipMalloc((void**)&tc, sizeof(int32_t) * (nsmax + 1)));
+    CHKB(hipMalloc((void**)&tmp, sizeof(int64_t) * (scan_tmp_elems(nsmax + 1) + 64)));
+    std::vector<int64_t> tcount((size_t)n, 0);
+    for (int i = 0; i < n; ++i) {
+        ebbkc_graph* g = b->graphs[(size_t)i];
+        const int k = b->ks[(size_t)i];
+        if (k < 3 || g->nseeds == 0) continue;
+        const int64_t ns = g->nseeds;
+        int64_t* to = nullptr;
+        CHKB(hipMalloc((void**)&to, sizeof(int64_t) * (ns + 1)));
+        hipLaunchKernelGGL(k_btask_counts, dim3(gridn(ns)), dim3(256), 0, s, g->seed_c, ns, k - 2, log_thr, tc);
+        CHKB(exclusive_scan_i32(tc, to, ns, to + ns, tmp, s));
+        CHKB(hipMemcpyAsync(&tcount[(size_t)i], to + ns, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        toffs[(size_t)i] = to;
+    }
+    CHKB(hipStreamSynchronize(s));
+    (void)hipFree(tc);
+    (void)hipFree(tmp);
+    for (int i = 0; i < n; ++i) {
+        gbase[(size_t)i] = total;
+        total += tcount[(size_t)i];
+    }
+    gbase[(size_t)n] = total;
+    b->ntasks = total;
+    if (total == 0) {
+        for (auto p : toffs) if (p) (void)hipFree(p);
+        return EBBKC_OK;
+    }
+    if (total >= ((int64_t)1 << 32)) return EBBKC_E_OOM;
+    int64_t *tasks = nullptr, *hist = nullptr, *htmp = nullptr;
+    int32_t* tg = nullptr;
+    uint64_t *keys = nullptr, *keys2 = nullptr;
+    uint32_t *vals = nullptr, *vals2 = nullptr;
+    const int64_t hn = radix_hist_elems(total);
+    CHKB(hipMalloc((void**)&tasks, sizeof(int64_t) * total));
+    CHKB(hipMalloc((void**)&tg, sizeof(int32_t) * total));
+    CHKB(hipMalloc((void**)&keys, sizeof(uint64_t) * total));
+    CHKB(hipMalloc((void**)&keys2, sizeof(uint64_t) * total));
+    CHKB(hipMalloc((void**)&vals, sizeof(uint32_t) * total));
+    CHKB(hipMalloc((void**)&vals2, sizeof(uint32_t) * total));
+    CHKB(hipMalloc((void**)&hist, sizeof(int64_t) * hn));
+    CHKB(hipMalloc((void**)&htmp, sizeof(int64_t) * (scan_tmp_elems(hn) + 64)));
+    for (int i = 0; i < n; ++i) {
+        if (!toffs[(size_t)i]) continue;
+        ebbkc_graph* g = b->graphs[(size_t)i];
+        hipLaunchKernelGGL(k_btask_fill, dim3(gridn(g->nseeds)), dim3(256), 0, s, g->seed_c, g->nseeds,
+                           b->ks[(size_t)i] - 2, log_thr, toffs[(size_t)i], gbase[(size_t)i], (int32_t)i, tasks, tg,
+                           keys, vals);
+    }
+    CHKB(radix_sort_u64(keys, vals, keys2, vals2, total, 10, hist, htmp, s));
+    CHKB(hipMalloc((void**)&b->tasks, sizeof(int64_t) * total));
+    CHKB(hipMalloc((void**)&b->tgraph, sizeof(int32_t) * total));
+    hipLaunchKernelGGL(k_bgather, dim3(gridn(total)), dim3(256), 0, s, tasks, tg, vals, total, b->tasks, b->tgraph);
+    CHKB(hipMemsetAsync(b->ctr, 0, 16 * sizeof(unsigned long long), s));
+    hipLaunchKernelGGL(k_bclass_hist, dim3(gridn(total)), dim3(256), 0, s, keys, total, b->ctr);
+    unsigned long long cc[4];
+    CHKB(hipMemcpyAsync(cc, b->ctr, sizeof(cc), hipMemcpyDeviceToHost, s));
+    CHKB(hipStreamSynchronize(s));
+    for (int w = 0; w < 4; ++w) b->ccount[w] = cc[w];
+    for (auto p : toffs) if (p) (void)hipFree(p);
+    void* ptrs[] = {tasks, tg, keys, keys2, vals, vals2, hist, htmp};
+    for (void* p : ptrs) (void)hipFree(p);
+    // frames for deep searches
+    if (b->kmax > 2 + 2 * LDS_FRAMES + 4) {
+        int64_t waves = 0;
+        for (int W = 1; W <= MAX_W; ++W)
+            waves = std::max(waves, search_grid_waves(W, false, total, b->cu_count, b->opt.blocks_per_cu));
+        CHKB(hipMalloc(&b->gframes, (size_t)waves * GLOBAL_FRAMES * search_frame_bytes(MAX_W)));
+    }
+    b->dirty = true;
+    return EBBKC_OK;
+}
+
+// The launch sequence: clear counters, one search per width class, copy the
+// per-graph totals and error flags to pinned host memory.
+ebbkc_status enqueue(ebbkc_batch* b, hipStream_t s) {
+    const int n = (int)b->graphs.size();
+    hipLaunchKernelGGL(k_bclear, dim3(gridn(16 + 2 * (int64_t)n)), dim3(256), 0, s, b->ctr, (int64_t)16, b->gtot,
+                       2 * (int64_t)n);
+    CHKB(hipGetLastError());
+    int64_t off = 0;
+    for (int W = 1; W <= MAX_W; ++W) {
+        const int64_t nt = (int64_t)b->ccount[W - 1];
+        if (!nt) continue;
+        SearchArgs a{};
+        a.tasks = b->tasks + off;
+        a.task_graph = b->tgraph + off;
+        a.ntasks = nt;
+        a.views = b->views;
+        a.graph_k = b->gk;
+        a.graph_total = b->gtot;
+        a.opts = opts_of(b->opt);
+        a.next = b->ctr + (W - 1);
+        a.total = b->ctr + 4;
+        a.work = b->ctr + 8;
+        a.err = (int*)(b->ctr + 6);
+        a.gframes = b->gframes;
+        CHKB(launch_search(W, false, a, b->cu_count, b->opt.blocks_per_cu, s));
+        off += nt;
+    }
+    CHKB(hipMemcpyAsync(b->h_tot, b->gtot, sizeof(unsigned long long) * 2 * n, hipMemcpyDeviceToHost, s));
+    CHKB(hipMemcpyAsync(b->h_ctr, b->ctr, sizeof(unsigned long long) * 16, hipMemcpyDeviceToHost, s));
+    return EBBKC_OK;
+}
+
+ebbkc_status capture(ebbkc_batch* b, hipStream_t s) {
+    if (b->exec) { (void)hipGraphExecDestroy(b->exec); b->exec = nullptr; }
+    if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
+    // capture on a private stream (the null stream cannot be captured)
+    hipStream_t cs;
+    CHKB(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    ebbkc_status st = EBBKC_OK;
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed) != hipSuccess) st = EBBKC_E_HIP;
+    if (!st) st = enqueue(b, cs);
+    hipGraph_t gr = nullptr;
+    if (hipStreamEndCapture(cs, &gr) != hipSuccess && !st) st = EBBKC_E_HIP;
+    if (!st && hipGraphInstantiate(&b->exec, gr, nullptr, nullptr, 0) != hipSuccess) st = EBBKC_E_HIP;
+    b->graph = gr;
+    (void)hipStreamDestroy(cs);
+    (void)s;
+    if (!st) b->dirty = false;
+    return st;
+}
+
+ebbkc_status finish(ebbkc_batch* b, uint64_t* out) {
+    const int n = (int)b->graphs.size();
+    const int err = (int)b->h_ctr[6];
+    if (err & ERR_WIDTH) return EBBKC_E_WIDTH;
+    if (err & ERR_DEPTH) return EBBKC_E_K_RANGE;
+    ebbkc_status st = EBBKC_OK;
+    for (int i = 0; i < n; ++i) {
+        const int k = b->ks[(size_t)i];
+        ebbkc_graph* g = b->graphs[(size_t)i];
+        uint64_t v;
+        if (k == 1) v = (uint64_t)g->n;
+        else if (k == 2) v = (uint64_t)g->m;
+        else if (k - 2 > g->tau) v = 0;
+        else {
+            if (b->h_tot[2 * i + 1] != 0 || (err & ERR_OVERFLOW)) st = EBBKC_E_OVERFLOW;
+            v = b->h_tot[2 * i];
+        }
+        if (out) out[i] = v;
+    }
+    return st;
+}
+
+std::mutex g_tune_mu;
+std::map<std::string, std::pair<int32_t, int32_t>> g_tune_cache;
+
+std::string signature(const ebbkc_batch* b) {
+    // graphs, total seeds (log2 bucket), k histogram
+    int64_t seeds = 0;
+    int hist[16] = {0};
+    for (size_t i = 0; i < b->graphs.size(); ++i) {
+        seeds += b->graphs[i]->nseeds;
+        hist[std::min(15, (int)b->ks[i])]++;
+    }
+    char buf[256];
+    int o = snprintf(buf, sizeof(buf), "n%zu_s%d", b->graphs.size(), seeds > 0 ? (int)std::log2((double)seeds) : 0);
+    for (int k = 3; k < 16; ++k)
+        if (hist[k]) o += snprintf(buf + o, sizeof(buf) - (size_t)o, "_k%d:%d", k, hist[k]);
+    return std::string(buf);
+}
+
+void load_cache_file() {
+    const char* path = getenv("EBBKC_TUNE_CACHE");
+    if (!path) return;
+    FILE* f = fopen(path, "r");
+    if (!f) return;
+    char key[256];
+    int a, c;
+    while (fscanf(f, "%255s %d %d", key, &a, &c) == 3) g_tune_cache[key] = {a, c};
+    fclose(f);
+}
+
+void save_cache_file() {
+    const char* path = getenv("EBBKC_TUNE_CACHE");
+    if (!path) return;
+    FILE* f = fopen(path, "w");
+    if (!f) return;
+    for (auto& kv : g_tune_cache) fprintf(f, "%s %d %d\n", kv.first.c_str(), kv.second.first, kv.second.second);
+    fclose(f);
+}
+
+}  // namespace
+}  // namespace ebb
+
+using namespace ebb;
+
+extern "C" {
+
+ebbkc_status ebbkc_batch_create(ebbkc_graph* const* graphs, const int32_t* ks, int32_t n, const ebbkc_options* opt,
+                                void* stream, ebbkc_batch** out) {
+    if (!graphs || !ks || n <= 0 || !out) return EBBKC_E_INVALID_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    ebbkc_batch* b = new ebbkc_batch();
+    b->graphs.assign(graphs, graphs + n);
+    b->ks.assign(ks, ks + n);
+    if (opt) b->opt = *opt; else ebbkc_default_options(&b->opt);
+    b->opt.count_work = 0;
+    (void)hipGetDevice(&b->device);
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, b->device) != hipSuccess) { delete b; return EBBKC_E_HIP; }
+    b->cu_count = prop.multiProcessorCount;
+    std::vector<ArenaView> views((size_t)n);
+    for (int i = 0; i < n; ++i) {
+        ebbkc_graph* g = graphs[i];
+        if (!g || g->device != b->device || ks[i] < 1 || ks[i] > MAX_K) { delete b; return EBBKC_E_INVALID_ARG; }
+        b->kmax = std::max(b->kmax, ks[i]);
+        if (ks[i] >= 3 && ks[i] - 2 <= g->tau) {
+            ebbkc_status st = arena_impl(g, s);
+            if (st) { delete b; return st; }
+        }
+        views[(size_t)i] = ArenaView{g->seed_eid, g->seed_c, g->row_off, g->vtx_off, g->arows, g->agid, g->acol};
+    }
+    // graphs whose k exceeds tau + 2 or is below 3 contribute no task
+    std::vector<int32_t> kk(b->ks);
+    for (int i = 0; i < n; ++i)
+        if (kk[(size_t)i] >= 3 && kk[(size_t)i] - 2 > graphs[i]->tau) kk[(size_t)i] = 0;
+    b->ks = kk;
+    auto fail = [&](ebbkc_status st) { ebbkc_batch_destroy(b); return st; };
+    if (hipMalloc((void**)&b->views, sizeof(ArenaView) * n) != hipSuccess) return fail(EBBKC_E_OOM);
+    if (hipMalloc((void**)&b->gk, sizeof(int32_t) * n) != hipSuccess) return fail(EBBKC_E_OOM);
+    if (hipMalloc((void**)&b->gtot, sizeof(unsigned long long) * 2 * n) != hipSuccess) return fail(EBBKC_E_OOM);
+    if (hipMalloc((void**)&b->ctr, sizeof(unsigned long long) * 16) != hipSuccess) return fail(EBBKC_E_OOM);
+    if (hipHostMalloc((void**)&b->h_tot, sizeof(unsigned long long) * 2 * n, hipHostMallocDefault) != hipSuccess)
+        return fail(EBBKC_E_OOM);
+    if (hipHostMalloc((void**)&b->h_ctr, sizeof(unsigned long long) * 16, hipHostMallocDefault) != hipSuccess)
+        return fail(EBBKC_E_OOM);
+    if (hipMemcpyAsync(b->views, views.data(), sizeof(ArenaView) * n, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(b->gk, b->ks.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s) != hipSuccess)
+        return fail(EBBKC_E_HIP);
+    if (ensure_tables(b->device, s) != hipSuccess) return fail(EBBKC_E_HIP);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        if (g_tune_cache.empty()) load_cache_file();
+        auto it = g_tune_cache.find(signature(b));
+        if (it != g_tune_cache.end() && !opt) {
+            b->opt.split_threshold = it->second.first;
+            b->opt.blocks_per_cu = it->second.second;
+        }
+    }
+    ebbkc_status st = build_tasks(b, s);
+    if (st) return fail(st);
+    *out = b;
+    return EBBKC_OK;
+}
+
+ebbkc_status ebbkc_batch_run(ebbkc_batch* b, int32_t use_graph, uint64_t* out_counts, void* stream) {
+    if (!b) return EBBKC_E_INVALID_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    auto t0 = std::chrono::steady_clock::now();
+    if (use_graph) {
+        if (b->dirty || !b->exec) {
+            ebbkc_status st = capture(b, s);
+            if (st) return st;
+        }
+        CHKB(hipGraphLaunch(b->exec, s));
+    } else {
+        ebbkc_status st = enqueue(b, s);
+        if (st) return st;
+    }
+    CHKB(hipStreamSynchronize(s));
+    b->last_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return finish(b, out_counts);
+}
+
+ebbkc_status ebbkc_batch_tune(ebbkc_batch* b, void* stream, int32_t* out_split, int32_t* out_blocks_per_cu) {
+    if (!b) return EBBKC_E_INVALID_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    const int32_t splits[] = {1 << 16, 1 << 22, 1 << 28, -1};
+    const int32_t bpcs[] = {0, 1, 2};
+    double best = 1e300;
+    int32_t bs = b->opt.split_threshold, bb = b->opt.blocks_per_cu;
+    std::vector<uint64_t> ref(b->graphs.size()), cur(b->graphs.size());
+    bool have_ref = false;
+    for (int32_t sp : splits) {
+        b->opt.split_threshold = sp;
+        ebbkc_status st = build_tasks(b, s);
+        if (st) return st;
+        for (int32_t bp : bpcs) {
+            b->opt.blocks_per_cu = bp;
+            st = ebbkc_batch_run(b, 0, cur.data(), stream);
+            if (st) return st;
+            if (!have_ref) { ref = cur; have_ref = true; }
+            else if (cur != ref) return EBBKC_E_HIP;  // every setting must give the same counts
+            if (b->last_ms < best) { best = b->last_ms; bs = sp; bb = bp; }
+        }
+    }
+    b->opt.split_threshold = bs;
+    b->opt.blocks_per_cu = bb;
+    ebbkc_status st = build_tasks(b, s);
+    if (st) return st;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune_cache[signature(b)] = {bs, bb};
+        save_cache_file();
+    }
+    if (out_split) *out_split = bs;
+    if (out_blocks_per_cu) *out_blocks_per_cu = bb;
+    return EBBKC_OK;
+}
+
+ebbkc_status ebbkc_batch_info(const ebbkc_batch* b, int64_t* out_tasks, double* out_last_ms) {
+    if (!b) return EBBKC_E_INVALID_ARG;
+    if (out_tasks) *out_tasks = b->ntasks;
+    if (out_last_ms) *out_last_ms = b->last_ms;
+    return EBBKC_OK;
+}
+
+void ebbkc_batch_destroy(ebbkc_batch* b) {
+    if (!b) return;
+    free_tasks(b);
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    void* ptrs[] = {b->views, b->gk, b->gtot, b->ctr};
+    for (void* p : ptrs) if (p) (void)hipFree(p);
+    if (b->h_tot) (void)hipHostFree(b->h_tot);
+    if (b->h_ctr) (void)hipHostFree(b->h_ctr);
+    delete b;
+}
+
+}  // extern "C"

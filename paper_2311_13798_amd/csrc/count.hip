@@ -185,6 +185,8 @@ struct DBuf {
 
 }  // namespace
 
+hipError_t ensure_tables(int dev, hipStream_t s) { return ensure_binom(dev, s); }
+
 #define CHKH(expr)                                                              \
     do {                                                                        \
         hipError_t e_ = (expr);                                                 \

@@ -73,6 +73,7 @@ ebbkc_status list_impl(ebbkc_graph* g, int32_t k, int64_t r_begin, int64_t r_end
                        uint32_t flags, uint64_t* out_written, uint64_t* out_checksums, hipStream_t s);
 ebbkc_status subsize_impl(ebbkc_graph* g, hipStream_t s);
 ebbkc_status arena_impl(ebbkc_graph* g, hipStream_t s);
+hipError_t ensure_tables(int dev, hipStream_t s);
 ebbkc_status count_seeds_impl(ebbkc_graph* g, int32_t k, const int64_t* eids, int64_t ne, int32_t ptr_kind,
                               uint64_t* out, hipStream_t s);
 void* scratch_get(ebbkc_graph* g, size_t bytes);

@@ -198,7 +198,7 @@ __global__ __launch_bounds__(256) void k_search(SearchArgs a) {
     // every lane writes them (identical values) and reads back its own stores
     auto FR = [&](int d) -> Frame<W>& { return d < LDS_FRAMES ? M.fr[d] : gfr[d - LDS_FRAMES]; };
     const int lane = lane_id();
-    const int k = a.k, opts = a.opts;
+    const int opts = a.opts;
     const bool rule1 = opts & OPT_RULE1, rule2 = opts & OPT_RULE2, et = opts & OPT_ET, t2 = opts & OPT_TPLEX2;
     const bool work = opts & OPT_WORK;
     Acc acc{0, 0};
@@ -212,14 +212,23 @@ __global__ __launch_bounds__(256) void k_search(SearchArgs a) {
         const int64_t task = a.tasks[it];
         const int64_t slot = task_slot(task);
         const int x0 = task_x0(task), x1 = task_x1(task);
-        const int c = uniform_i32(a.A.seed_c[slot]);
-        const int64_t ro = a.A.row_off[slot], vo = a.A.vtx_off[slot];
+        const int gi = a.task_graph ? uniform_i32(a.task_graph[it]) : 0;
+        const ArenaView& A = a.views ? a.views[gi] : a.A;
+        const int k = a.graph_k ? uniform_i32(a.graph_k[gi]) : a.k;
+        const int c = uniform_i32(A.seed_c[slot]);
+        const int64_t ro = A.row_off[slot], vo = A.vtx_off[slot];
         wk_tasks += work;
+        Acc tacc{0, 0};
+        if (k == 3) {  // l = 1 at the root: |V(g_i)| triangles through the seed edge
+            tacc.add((uint64_t)c);
+            goto task_done;
+        }
 
         // ---- load the sub-branch into LDS (coalesced)
-        for (int i = lane; i < c * W; i += 64) (&M.rows[0][0])[i] = a.A.rows[ro + i];
-        for (int i = lane; i < c; i += 64) M.col[i] = a.A.col[vo + i];
+        for (int i = lane; i < c * W; i += 64) (&M.rows[0][0])[i] = A.rows[ro + i];
+        for (int i = lane; i < c; i += 64) M.col[i] = A.col[vo + i];
         wave_sync();
+        {
         // lane-owned symmetric rows; colour class lane + 64 q (colour lane + 64 q + 1)
         // occupies relabelled positions [#(col > colour), #(col >= colour))
         uint64_t srow[W][W], cls[W][W];
@@ -247,7 +256,6 @@ __global__ __launch_bounds__(256) void k_search(SearchArgs a) {
                 cls[q][w] = mk;
             }
         }
-        Acc tacc{0, 0};
 
         // Count a node that needs no branching: returns true and sets val, or
         // false when the node (l >= 4) must be branched on.
@@ -469,12 +477,22 @@ __global__ __launch_bounds__(256) void k_search(SearchArgs a) {
             l = lc;
         }
 
+        }
+    task_done:
         if (tacc.hi && lane == 0) atomicOr(a.err, ERR_OVERFLOW);
         if (a.per_task && lane == 0) a.per_task[it] = tacc.lo;
-        const uint64_t o = acc.lo;
-        acc.lo += tacc.lo;
-        if (acc.lo < o) ++acc.hi;
-        acc.hi += tacc.hi;
+        if (a.graph_total) {
+            if (lane == 0 && tacc.lo) {
+                const unsigned long long old = atomicAdd(&a.graph_total[2 * gi], (unsigned long long)tacc.lo);
+                if (old + tacc.lo < old) atomicAdd(&a.graph_total[2 * gi + 1], 1ull);
+            }
+            if (lane == 0 && tacc.hi) atomicAdd(&a.graph_total[2 * gi + 1], (unsigned long long)tacc.hi);
+        } else {
+            const uint64_t o = acc.lo;
+            acc.lo += tacc.lo;
+            if (acc.lo < o) ++acc.hi;
+            acc.hi += tacc.hi;
+        }
         wave_sync();
     }
     if (work && lane == 0) {
