@@ -196,6 +196,40 @@ ebbkc_status ebbkc_batch_info(const ebbkc_batch *b, int64_t *out_tasks, double *
 
 void ebbkc_batch_destroy(ebbkc_batch *b);
 
+/* ---- Served form: continuous batching of count requests.
+ * A catalogue of prepared graphs stays resident in device memory; requests
+ * (graph index, k) are submitted as they arrive.  A worker thread runs
+ * epochs: each takes the waiting requests in arrival order while their
+ * estimated device footprint fits budget_bytes (a request larger than the
+ * budget runs alone) and counts them all in one fused batched launch;
+ * requests arriving meanwhile join the next epoch.  Results are exact and do
+ * not depend on which requests share an epoch.  Times are milliseconds since
+ * the server was created (host steady clock). */
+typedef struct ebbkc_server ebbkc_server;
+
+typedef struct {
+    int64_t id;
+    int32_t graph, k;
+    int32_t status;     /* ebbkc_status of the request */
+    int32_t pad;
+    uint64_t count;     /* exact k-clique count (valid when status == EBBKC_OK) */
+    double arrival_ms;  /* submission */
+    double admit_ms;    /* start of the epoch that ran it */
+    double done_ms;     /* result available */
+} ebbkc_result;
+
+/* graphs: the catalogue (handles must outlive the server and not be used
+ * elsewhere while it runs).  Builds the sub-branch arenas up front. */
+ebbkc_status ebbkc_server_create(ebbkc_graph *const *graphs, int32_t n, const ebbkc_options *opt,
+                                 int64_t budget_bytes, ebbkc_server **out);
+ebbkc_status ebbkc_server_submit(ebbkc_server *s, int32_t graph, int32_t k, int64_t *out_id);
+/* Move up to max completed results to out (*n_out of them); wait = 1 blocks
+ * until at least one is available or nothing is pending. */
+ebbkc_status ebbkc_server_poll(ebbkc_server *s, ebbkc_result *out, int32_t max, int32_t wait, int32_t *n_out);
+/* [requests submitted, epochs run, most requests in one epoch, requests waiting or running] */
+ebbkc_status ebbkc_server_stats(const ebbkc_server *s, int64_t out[4]);
+void ebbkc_server_destroy(ebbkc_server *s);
+
 const char *ebbkc_strerror(ebbkc_status s);
 
 #ifdef __cplusplus

@@ -36,6 +36,12 @@ class ebbkc_options(ctypes.Structure):
                 ("reserved", ctypes.c_int32 * 7)]
 
 
+class ebbkc_result(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_int64), ("graph", ctypes.c_int32), ("k", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("pad", ctypes.c_int32), ("count", ctypes.c_uint64), ("arrival_ms", ctypes.c_double),
+                ("admit_ms", ctypes.c_double), ("done_ms", ctypes.c_double)]
+
+
 class ebbkc_info(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("m", ctypes.c_int64), ("tau", ctypes.c_int32), ("rounds", ctypes.c_int32),
                 ("max_degree", ctypes.c_int32), ("device_bytes", ctypes.c_int64), ("prepare_ms", ctypes.c_double)]
@@ -44,7 +50,8 @@ class ebbkc_info(ctypes.Structure):
 EXPORTED = ("ebbkc_default_options", "ebbkc_prepare", "ebbkc_count", "ebbkc_count_range", "ebbkc_count_seeds",
             "ebbkc_list", "ebbkc_export", "ebbkc_info_get", "ebbkc_last_timing", "ebbkc_last_work", "ebbkc_destroy",
             "ebbkc_strerror", "ebbkc_batch_create", "ebbkc_batch_run", "ebbkc_batch_tune", "ebbkc_batch_info",
-            "ebbkc_batch_destroy")
+            "ebbkc_batch_destroy", "ebbkc_server_create", "ebbkc_server_submit", "ebbkc_server_poll",
+            "ebbkc_server_stats", "ebbkc_server_destroy")
 
 _lib = None
 
@@ -79,6 +86,14 @@ def load_library(path: str = LIB_PATH):
     lib.ebbkc_batch_destroy.argtypes = [vp]
     lib.ebbkc_batch_destroy.restype = None
     for f in ("ebbkc_batch_create", "ebbkc_batch_run", "ebbkc_batch_tune", "ebbkc_batch_info"):
+        getattr(lib, f).restype = ctypes.c_int
+    lib.ebbkc_server_create.argtypes = [vp, i32, ctypes.POINTER(ebbkc_options), i64, ctypes.POINTER(vp)]
+    lib.ebbkc_server_submit.argtypes = [vp, i32, i32, ctypes.POINTER(ctypes.c_int64)]
+    lib.ebbkc_server_poll.argtypes = [vp, ctypes.POINTER(ebbkc_result), i32, i32, ctypes.POINTER(ctypes.c_int32)]
+    lib.ebbkc_server_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
+    lib.ebbkc_server_destroy.argtypes = [vp]
+    lib.ebbkc_server_destroy.restype = None
+    for f in ("ebbkc_server_create", "ebbkc_server_submit", "ebbkc_server_poll", "ebbkc_server_stats"):
         getattr(lib, f).restype = ctypes.c_int
     lib.ebbkc_strerror.argtypes = [i32]
     lib.ebbkc_strerror.restype = ctypes.c_char_p
@@ -267,6 +282,39 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def ebbkc_server_create(handles, budget_bytes: int, options: ebbkc_options | None = None):
+    n = len(handles)
+    arr = (ctypes.c_void_p * n)(*[h.value if isinstance(h, ctypes.c_void_p) else h for h in handles])
+    s = ctypes.c_void_p()
+    _check(load_library().ebbkc_server_create(arr, n, ctypes.byref(options) if options else None, int(budget_bytes),
+                                              ctypes.byref(s)), "ebbkc_server_create")
+    return s
+
+
+def ebbkc_server_submit(s, graph: int, k: int) -> int:
+    rid = ctypes.c_int64()
+    _check(load_library().ebbkc_server_submit(s, graph, k, ctypes.byref(rid)), "ebbkc_server_submit")
+    return int(rid.value)
+
+
+def ebbkc_server_poll(s, max_results: int = 4096, wait: bool = False):
+    buf = (ebbkc_result * max_results)()
+    n = ctypes.c_int32()
+    _check(load_library().ebbkc_server_poll(s, buf, max_results, int(wait), ctypes.byref(n)), "ebbkc_server_poll")
+    return [dict(id=r.id, graph=r.graph, k=r.k, status=r.status, count=int(r.count), arrival_ms=r.arrival_ms,
+                 admit_ms=r.admit_ms, done_ms=r.done_ms) for r in buf[: n.value]]
+
+
+def ebbkc_server_stats(s):
+    out = (ctypes.c_int64 * 4)()
+    _check(load_library().ebbkc_server_stats(s, out), "ebbkc_server_stats")
+    return [int(x) for x in out]
+
+
+def ebbkc_server_destroy(s):
+    load_library().ebbkc_server_destroy(s)
 
 
 # ---------------------------------------------------------------- convenience wrapper

@@ -497,3 +497,175 @@ void ebbkc_batch_destroy(ebbkc_batch* b) {
 }
 
 }  // extern "C"
+
+// ============================================================== served form
+//
+// A catalogue of prepared graphs stays resident; requests (graph, k) are
+// submitted as they arrive and a worker thread runs them in epochs: every
+// epoch takes the waiting requests in arrival order while their estimated
+// device footprint fits the budget (a request larger than the budget runs
+// alone), merges their task lists and runs one fused launch per width class.
+// Requests arriving while an epoch runs join the next one.  Footprint of a
+// request: 16 bytes per task (task word, graph id, sort key) plus, for each
+// resident wave, one c x c bitmap of the graph's largest sub-branch
+// (~tau^2 bits per live branch).
+
+#include <condition_variable>
+#include <deque>
+#include <thread>
+
+struct ebbkc_server {
+    std::vector<ebbkc_graph*> cat;
+    std::vector<int64_t> branch_bytes;  // per graph: tau^2 / 8 bytes
+    ebbkc_options opt{};
+    int64_t budget = 0;
+    hipStream_t stream = nullptr;
+    std::thread worker;
+    std::mutex mu;
+    std::condition_variable cv, done_cv;
+    bool stop = false;
+    std::deque<ebbkc_result> pending;
+    std::vector<ebbkc_result> done;
+    int64_t next_id = 0, in_flight = 0, epochs = 0, max_epoch_requests = 0;
+    std::chrono::steady_clock::time_point t0;
+    double now_ms() const {
+        return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+};
+
+namespace ebb {
+namespace {
+
+int64_t request_bytes(const ebbkc_server* S, const ebbkc_result& r) {
+    const ebbkc_graph* g = S->cat[(size_t)r.graph];
+    const int64_t waves = 4096;  // resident waves of a persistent launch (upper bound)
+    return 16 * (g->nseeds + 1) + waves * S->branch_bytes[(size_t)r.graph];
+}
+
+void serve_loop(ebbkc_server* S) {
+    (void)hipSetDevice(S->cat.empty() ? 0 : S->cat[0]->device);
+    for (;;) {
+        std::vector<ebbkc_result> epoch;
+        {
+            std::unique_lock<std::mutex> lk(S->mu);
+            S->cv.wait(lk, [&] { return S->stop || !S->pending.empty(); });
+            if (S->stop && S->pending.empty()) return;
+            int64_t used = 0;
+            while (!S->pending.empty()) {
+                const int64_t need = request_bytes(S, S->pending.front());
+                if (!epoch.empty() && used + need > S->budget) break;
+                used += need;
+                epoch.push_back(S->pending.front());
+                S->pending.pop_front();
+            }
+            S->in_flight = (int64_t)epoch.size();
+        }
+        const double t_admit = S->now_ms();
+        std::vector<ebbkc_graph*> gs;
+        std::vector<int32_t> ks;
+        for (auto& r : epoch) {
+            r.admit_ms = t_admit;
+            gs.push_back(S->cat[(size_t)r.graph]);
+            ks.push_back(r.k);
+        }
+        ebbkc_batch* b = nullptr;
+        std::vector<uint64_t> cnt(epoch.size(), 0);
+        ebbkc_status st = ebbkc_batch_create(gs.data(), ks.data(), (int32_t)gs.size(), &S->opt, S->stream, &b);
+        if (!st) st = ebbkc_batch_run(b, 0, cnt.data(), S->stream);
+        if (b) ebbkc_batch_destroy(b);
+        const double t_done = S->now_ms();
+        {
+            std::lock_guard<std::mutex> lk(S->mu);
+            for (size_t i = 0; i < epoch.size(); ++i) {
+                epoch[i].status = st;
+                epoch[i].count = st ? 0 : cnt[i];
+                epoch[i].done_ms = t_done;
+                S->done.push_back(epoch[i]);
+            }
+            S->in_flight = 0;
+            S->epochs++;
+            S->max_epoch_requests = std::max<int64_t>(S->max_epoch_requests, (int64_t)epoch.size());
+        }
+        S->done_cv.notify_all();
+    }
+}
+
+}  // namespace
+}  // namespace ebb
+
+extern "C" {
+
+ebbkc_status ebbkc_server_create(ebbkc_graph* const* graphs, int32_t n, const ebbkc_options* opt, int64_t budget_bytes,
+                                 ebbkc_server** out) {
+    if (!graphs || n <= 0 || !out || budget_bytes <= 0) return EBBKC_E_INVALID_ARG;
+    ebbkc_server* S = new ebbkc_server();
+    S->cat.assign(graphs, graphs + n);
+    if (opt) S->opt = *opt; else ebbkc_default_options(&S->opt);
+    S->budget = budget_bytes;
+    for (int i = 0; i < n; ++i) {
+        if (!graphs[i]) { delete S; return EBBKC_E_INVALID_ARG; }
+        const int64_t t = graphs[i]->tau + 2;
+        S->branch_bytes.push_back((t * t + 7) / 8);
+        if (graphs[i]->tau >= 1) {
+            ebbkc_status st = ebb::arena_impl(graphs[i], nullptr);  // resident before the first request
+            if (st) { delete S; return st; }
+        }
+    }
+    if (hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking) != hipSuccess) { delete S; return EBBKC_E_HIP; }
+    S->t0 = std::chrono::steady_clock::now();
+    S->worker = std::thread(ebb::serve_loop, S);
+    *out = S;
+    return EBBKC_OK;
+}
+
+ebbkc_status ebbkc_server_submit(ebbkc_server* S, int32_t graph, int32_t k, int64_t* out_id) {
+    if (!S || graph < 0 || graph >= (int32_t)S->cat.size() || k < 1) return EBBKC_E_INVALID_ARG;
+    ebbkc_result r{};
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        r.id = S->next_id++;
+        r.graph = graph;
+        r.k = k;
+        r.arrival_ms = S->now_ms();
+        S->pending.push_back(r);
+    }
+    S->cv.notify_one();
+    if (out_id) *out_id = r.id;
+    return EBBKC_OK;
+}
+
+ebbkc_status ebbkc_server_poll(ebbkc_server* S, ebbkc_result* out, int32_t max, int32_t wait, int32_t* n_out) {
+    if (!S || !n_out || (max > 0 && !out)) return EBBKC_E_INVALID_ARG;
+    std::unique_lock<std::mutex> lk(S->mu);
+    if (wait) S->done_cv.wait(lk, [&] { return !S->done.empty() || (S->pending.empty() && S->in_flight == 0); });
+    const int32_t n = (int32_t)std::min<size_t>((size_t)max, S->done.size());
+    for (int32_t i = 0; i < n; ++i) out[i] = S->done[(size_t)i];
+    S->done.erase(S->done.begin(), S->done.begin() + n);
+    *n_out = n;
+    return EBBKC_OK;
+}
+
+ebbkc_status ebbkc_server_stats(const ebbkc_server* S, int64_t out[4]) {
+    if (!S || !out) return EBBKC_E_INVALID_ARG;
+    ebbkc_server* M = const_cast<ebbkc_server*>(S);
+    std::lock_guard<std::mutex> lk(M->mu);
+    out[0] = S->next_id;
+    out[1] = S->epochs;
+    out[2] = S->max_epoch_requests;
+    out[3] = (int64_t)S->pending.size() + S->in_flight;
+    return EBBKC_OK;
+}
+
+void ebbkc_server_destroy(ebbkc_server* S) {
+    if (!S) return;
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->stop = true;
+    }
+    S->cv.notify_all();
+    if (S->worker.joinable()) S->worker.join();
+    if (S->stream) (void)hipStreamDestroy(S->stream);
+    delete S;
+}
+
+}  // extern "C"
