@@ -73,7 +73,10 @@ typedef struct {
     int32_t blocks_per_cu;     /* persistent workgroups per compute unit (0 = auto) */
     int32_t split_threshold;   /* root-branch work above which a seed is split (0 = auto, <0 = never) */
     int32_t count_work;        /* 1: record search work counters (ebbkc_last_work); default 0 */
-    int32_t reserved[7];
+    int32_t dense_k4;          /* 4-cliques of a dense candidate set counted from its missing pairs
+                                  when that costs less than branching: weight (percent) of its cost
+                                  estimate, 0 = default (100), < 0 = never */
+    int32_t reserved[6];
 } ebbkc_options;
 
 typedef struct {

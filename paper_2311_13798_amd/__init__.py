@@ -33,7 +33,7 @@ class ebbkc_options(ctypes.Structure):
     _fields_ = [("early_termination", ctypes.c_int32), ("t_plex", ctypes.c_int32), ("rule1", ctypes.c_int32),
                 ("rule2", ctypes.c_int32), ("waves_per_block", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
                 ("split_threshold", ctypes.c_int32), ("count_work", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 7)]
+                ("dense_k4", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6)]
 
 
 class ebbkc_result(ctypes.Structure):

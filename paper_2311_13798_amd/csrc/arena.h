@@ -71,6 +71,7 @@ struct SearchArgs {
     int64_t ntasks;
     int32_t k;
     int32_t opts;
+    float k4_weight;            // dense 4-clique evaluation cost weight (<= 0: never)
     unsigned long long* next;
     unsigned long long* total;  // [lo, hi]
     unsigned long long* work;   // [tasks, nodes, word ops]
@@ -96,6 +97,7 @@ hipError_t launch_search(int W, bool list, const SearchArgs& a, int cus, int blo
 int64_t search_grid_waves(int W, bool list, int64_t ntasks, int cus, int blocks_per_cu);
 size_t search_frame_bytes(int W);
 hipError_t launch_binom_init(hipStream_t s);
+float k4_weight_of(int32_t dense_k4);
 hipError_t launch_list(int W, const SearchArgs& a, int cus, hipStream_t s);
 size_t list_frame_bytes(int W);
 int64_t list_grid_waves(int W, int64_t ntasks, int cus);

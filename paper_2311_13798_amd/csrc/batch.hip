@@ -266,6 +266,7 @@ ebbkc_status enqueue(ebbkc_batch* b, hipStream_t s) {
         a.graph_k = b->gk;
         a.graph_total = b->gtot;
         a.opts = opts_of(b->opt);
+        a.k4_weight = k4_weight_of(b->opt.dense_k4);
         a.next = b->ctr + (W - 1);
         a.total = b->ctr + 4;
         a.work = b->ctr + 8;

@@ -411,6 +411,7 @@ static ebbkc_status run_tasks(ebbkc_graph* g, int32_t k, const int64_t* tsorted,
         a.ntasks = nt;
         a.k = k;
         a.opts = opts_of(g->opt);
+        a.k4_weight = k4_weight_of(g->opt.dense_k4);
         a.next = (unsigned long long*)(g->d_counters + W - 1);
         a.total = (unsigned long long*)(g->d_counters + 4);
         a.work = (unsigned long long*)(g->d_counters + 8);

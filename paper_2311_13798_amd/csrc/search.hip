@@ -103,6 +103,7 @@ template <int W>
 struct SearchMem {
     uint64_t rows[64 * W][W];
     int16_t col[64 * W];
+    int16_t md[64 * W];  // missing pairs per vertex inside the set being counted
     Frame<W> fr[LDS_FRAMES];
 };
 
@@ -331,13 +332,150 @@ __global__ __launch_bounds__(256) void k_search(SearchArgs a) {
             return true;
         };
 
-        // children of a node with l = 5 (l = 4), x in [xlo, xhi), counted by
-        // lanes: lane j of chunk q takes y = 64 q + j
+        // 4-cliques inside R (r >= 4 vertices) from the missing pairs H of R:
+        // inclusion-exclusion over the edge sets of H spanning at most four
+        // vertices gives K4 = C(r,4) - M C(r-2,2) + P3 (r-3) + 2K2 - T (r-3)
+        // - P4 - S3 + C4 + paw - diamond + K4(H), with P3 the 2-paths, 2K2
+        // the disjoint pairs, T the triangles, P4 the 3-paths, S3 the 3-stars,
+        // C4 the 4-cycles, paw, diamond and K4(H) the remaining 4-vertex
+        // shapes of H.  All but C(r,4) + C(M,2) is a sum over the vertices,
+        // missing pairs and 2-paths of H, taken by the lanes owning them into
+        // S (12 times its value, so that every term is an integer).  Returns
+        // false, counting nothing, when H is too dense for this to beat
+        // branching on the pairs of R.
+        auto k4_missing = [&](const uint64_t (&R)[W], int r, bool whole, int64_t& S, uint64_t& uacc, uint64_t& ops) -> bool {
+            int msum = 0, cm2 = 0, lw = 0;
+#pragma unroll
+            for (int q = 0; q < W; ++q) {
+                if ((R[q] >> lane) & 1) {
+                    int mv = -1;  // R & ~row(v) holds v itself
+#pragma unroll
+                    for (int w = 0; w < W; ++w) mv += popc64(R[w] & ~srow[q][w]);
+                    M.md[lane + 64 * q] = (int16_t)mv;
+                    msum += mv;
+                    cm2 += mv * (mv - 1) / 2;
+                    lw += mv + mv * (mv - 1) / 2;
+                }
+            }
+            const uint64_t pk = wave_sum(((uint64_t)cm2 << 24) | (uint64_t)msum);
+            const int Msum = uniform_i32((int)(pk & 0xFFFFFF));
+            const int64_t P3 = (int64_t)uni64(pk >> 24);
+            // The lanes run in lockstep, so this evaluation takes as long as
+            // its busiest lane (missing pairs + 2-paths at the vertices it
+            // owns, ~15 instructions each) plus ~150 for the reductions.  The
+            // alternative for one R = P & N+(x) of an l = 5 node is one child
+            // y per lane counting the triangles of R & N+(y): a lane step
+            // (~35 instructions) per vertex of the largest child, ~ r * d,
+            // per 64-vertex chunk of R; for a whole l = 4 node it is that
+            // for every x (~18 instructions a step), ~ |E(R)| * d.
+            const int lmax = uniform_i32(wave_max(lw));
+            const float pairs = 0.5f * (float)r * (float)(r - 1);
+            const float E = pairs - 0.5f * (float)Msum, d = E / pairs;
+            const float cost = a.k4_weight * (15.0f * (float)lmax + 150.0f);
+            const float alt = whole ? 18.0f * E * d : 35.0f * (float)r * d * (float)((r + 63) >> 6);
+            if (!(a.k4_weight > 0.f) || cost > alt) return false;
+            if (work) ops += (uint64_t)(r + Msum + P3) * W;
+            const int64_t Mh = Msum / 2;
+            uacc += binom(r, 4) + (uint64_t)(Mh * (Mh - 1) / 2);
+            if (Msum == 0) return true;
+            wave_sync();  // md[] of every vertex of R
+            const int64_t c2 = (int64_t)(r - 2) * (r - 3) / 2;
+#pragma unroll
+            for (int q = 0; q < W; ++q) {
+                if (!((R[q] >> lane) & 1)) continue;
+                const int v = lane + 64 * q;
+                uint64_t hv[W];
+#pragma unroll
+                for (int w = 0; w < W; ++w) hv[w] = R[w] & ~srow[q][w] & (w == q ? ~(1ull << lane) : ~0ull);
+                const int64_t mv = M.md[v];
+                if (mv == 0) continue;
+                S += -6 * c2 * mv + 12 * (int64_t)(r - 4) * (mv * (mv - 1) / 2) - 2 * mv * (mv - 1) * (mv - 2);
+                int64_t t2 = 0;
+                // missing pairs v-u: codegree in H, triangles, diamonds, 3-paths, K4(H)
+#pragma unroll
+                for (int wu = 0; wu < W; ++wu) {
+                    uint64_t bu = hv[wu];
+                    while (bu) {
+                        const int u = wu * 64 + __builtin_ctzll(bu);
+                        bu &= bu - 1;
+                        uint64_t hu[W];
+#pragma unroll
+                        for (int w = 0; w < W; ++w) hu[w] = R[w] & ~M.rows[u][w];
+                        int cc = -1;  // u lies in both hv and hu
+#pragma unroll
+                        for (int w = 0; w < W; ++w) cc += popc64(hv[w] & hu[w]);
+                        t2 += cc;
+                        if (u > v) {
+                            const int64_t mu = M.md[u];
+                            S += -4 * (int64_t)(r - 3) * cc + 12 * (cc - (mu - 1) * (mv - 1)) -
+                                 6 * (int64_t)cc * (cc - 1);
+                            if (cc >= 2) {
+                                uint64_t X[W];
+#pragma unroll
+                                for (int w = 0; w < W; ++w) X[w] = hv[w] & hu[w] & upper_mask(u, w);
+#pragma unroll
+                                for (int wx = 0; wx < W; ++wx) {
+                                    while (X[wx]) {
+                                        const int z = wx * 64 + __builtin_ctzll(X[wx]);
+                                        X[wx] &= X[wx] - 1;
+                                        int kk = 0;
+#pragma unroll
+                                        for (int w = 0; w < W; ++w)
+                                            if (w >= wx) kk += popc64(X[w] & ~M.rows[z][w]);
+                                        S += 12 * kk;
+                                    }
+                                }
+                            }
+                        }
+                    }
+                }
+                S += 6 * t2 * (mv - 2);
+                // 2-paths a-v-b (a < b): 4 C4 = sum (codeg(a,b) - 1)
+#pragma unroll
+                for (int wa = 0; wa < W; ++wa) {
+                    uint64_t ba = hv[wa];
+                    while (ba) {
+                        const int a0 = wa * 64 + __builtin_ctzll(ba);
+                        ba &= ba - 1;
+                        uint64_t ha[W], rest[W];
+#pragma unroll
+                        for (int w = 0; w < W; ++w) {
+                            ha[w] = R[w] & ~M.rows[a0][w];
+                            rest[w] = hv[w] & upper_mask(a0, w);
+                        }
+#pragma unroll
+                        for (int wb = 0; wb < W; ++wb) {
+                            if (wb < wa) continue;
+                            while (rest[wb]) {
+                                const int b = wb * 64 + __builtin_ctzll(rest[wb]);
+                                rest[wb] &= rest[wb] - 1;
+                                int cd = (ha[wb] >> (b & 63)) & 1 ? -3 : -1;  // a, b themselves when a-b is missing
+#pragma unroll
+                                for (int w = 0; w < W; ++w) cd += popc64(ha[w] & ~M.rows[b][w]);
+                                S += 3 * cd;
+                            }
+                        }
+                    }
+                }
+            }
+            return true;
+        };
+
+        // children of a node with l = 5 (l = 4), x in [xlo, xhi): the
+        // 4-cliques (triangles) of R = P & N+(x) for each x.  A dense R is
+        // counted by the wave from its missing pairs; otherwise lane j of
+        // chunk q takes the child y = 64 q + j.
         auto children_by_lanes = [&](const uint64_t (&P)[W], int l, int xlo, int xhi) {
-            uint64_t lsum = 0, lops = 0;
+            uint64_t lsum = 0, lops = 0, usum = 0;
+            int64_t S = 0;
             const int lc = l - 2;
+            bool done = false;
+            if (l == 4 && xlo == 0 && xhi >= c) {
+                const int pc = popcW(P);
+                done = pc < 4 || k4_missing(P, pc, true, S, usum, lops);
+            }
             int xx = xlo - 1;
-            while (true) {
+            while (!done) {
                 int nx = -1;
 #pragma unroll
                 for (int w = W - 1; w >= 0; --w) {
@@ -352,6 +490,7 @@ __global__ __launch_bounds__(256) void k_search(SearchArgs a) {
                 const int rc = popcW(Rx);
                 if (rc < lc + 1) continue;
                 if (work) { wk_nodes += rc; wk_ops += (uint64_t)rc * W; }
+                if (l == 5 && k4_missing(Rx, rc, false, S, usum, lops)) continue;
 #pragma unroll
                 for (int q = 0; q < W; ++q) {
                     if (Rx[q] == 0) continue;
@@ -367,7 +506,8 @@ __global__ __launch_bounds__(256) void k_search(SearchArgs a) {
                 }
             }
             if (work) wk_ops += wave_sum(lops);
-            tacc.add(wave_sum(lsum));
+            const int64_t s12 = wave_sum(S);
+            tacc.add((uint64_t)((int64_t)(wave_sum(lsum) + usum) + s12 / 12));
         };
 
         const int l0 = k - 2;
@@ -569,6 +709,8 @@ size_t search_frame_bytes(int W) {
     }
     return 0;
 }
+
+float k4_weight_of(int32_t dense_k4) { return dense_k4 < 0 ? 0.f : (dense_k4 == 0 ? 1.f : 0.01f * (float)dense_k4); }
 
 hipError_t launch_binom_init(hipStream_t s) {
     hipLaunchKernelGGL(k_binom_init, dim3((BIN_N + 255) / 256), dim3(256), 0, s);

@@ -205,3 +205,44 @@ def test_er_small_golden(ebb):
     for k, v in fx["counts"].items():
         assert G.count(int(k)) == v
     G.close()
+
+
+def elementary_symmetric(parts, k):
+    e = [1] + [0] * k
+    for a in parts:
+        for j in range(k, 0, -1):
+            e[j] += e[j - 1] * a
+    return e[k]
+
+
+@pytest.mark.parametrize("parts,kmax", [([4] * 12, 12), ([5, 4, 3, 6, 2, 7, 4, 5, 3, 3], 10), ([6] * 20, 8),
+                                        ([4] * 45, 7), ([3] * 80, 6), ([2] * 30 + [5] * 12, 8)],
+                         ids=["4x12", "mixed10", "6x20", "4x45", "3x80", "2x30_5x12"])
+def test_complete_multipartite_closed_form(ebb, parts, kmax):
+    # the missing pairs form disjoint cliques (triangles, diamonds and K4s among them for parts
+    # of 4 and more): N_k is the k-th elementary symmetric polynomial of the part sizes
+    g = graphgen.complete_multipartite(parts)
+    G = ebb.Graph.from_csr(g)
+    for k in range(1, kmax + 1):
+        print(f"case multipartite {len(parts)} parts k={k}", flush=True)
+        assert G.count(k) == elementary_symmetric(parts, k), (parts, k)
+    G.close()
+
+
+@pytest.mark.parametrize("n,pm,kmax", [(30, 0.05, 9), (40, 0.15, 8), (40, 0.3, 8), (70, 0.03, 8), (70, 0.1, 8),
+                                      (130, 0.05, 6), (200, 0.04, 6), (250, 0.03, 5)])
+def test_near_cliques_match_oracle(ebb, n, pm, kmax):
+    # the complement of a sparse random graph: every candidate set is dense, so 4-cliques are
+    # counted from the missing pairs; also with that evaluation switched off
+    h = graphgen.er(n, pm, seed=int(1000 * pm) + n)
+    edges = set(map(tuple, h.edges().tolist()))
+    g = graphgen.from_edges(n, [[a, b] for a in range(n) for b in range(a + 1, n) if (a, b) not in edges])
+    G = ebb.Graph.from_csr(g)
+    G0 = ebb.Graph.from_csr(g, options=opts(ebb, dense_k4=-1))
+    for k in range(3, kmax + 1):
+        print(f"case near-clique n={n} pm={pm} k={k}", flush=True)
+        want = oracle.count(g, k)
+        assert G.count(k) == want, (n, pm, k)
+        assert G0.count(k) == want, (n, pm, k)
+    G.close()
+    G0.close()
