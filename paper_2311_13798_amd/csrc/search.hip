@@ -103,7 +103,9 @@ template <int W>
 struct SearchMem {
     uint64_t rows[64 * W][W];
     int16_t col[64 * W];
-    int16_t md[64 * W];  // missing pairs per vertex inside the set being counted
+    int16_t md[64 * W];      // missing pairs per vertex inside the set being counted
+    int16_t vl[64 * W];      // that set's vertices in order, one per lane
+    int32_t pq[64 + 64 * W];  // queued children x << 16 | y of the node being counted
     Frame<W> fr[LDS_FRAMES];
 };
 
@@ -189,7 +191,7 @@ __device__ __forceinline__ uint64_t lane_triangles(const SearchMem<W>& M, const 
 }  // namespace
 
 template <int W, bool LIST>
-__global__ __launch_bounds__(256) void k_search(SearchArgs a) {
+__global__ __launch_bounds__(256, (W <= 3 ? 3 : 2)) void k_search(SearchArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     SearchMem<W>& M = reinterpret_cast<SearchMem<W>*>(smem_raw)[threadIdx.x / 64];
     Frame<W>* gfr = a.gframes ? reinterpret_cast<Frame<W>*>(a.gframes) +
@@ -230,32 +232,21 @@ __global__ __launch_bounds__(256) void k_search(SearchArgs a) {
         for (int i = lane; i < c; i += 64) M.col[i] = A.col[vo + i];
         wave_sync();
         {
-        // lane-owned symmetric rows; colour class lane + 64 q (colour lane + 64 q + 1)
-        // occupies relabelled positions [#(col > colour), #(col >= colour))
-        uint64_t srow[W][W], cls[W][W];
+        // colour class lane + 64 q (colour lane + 64 q + 1) occupies the
+        // relabelled positions [cs0[q], cs1[q]) = [#(col > colour), #(col >= colour))
+        int cs0[W], cs1[W];
         const int ncol = uniform_i32(M.col[0]);
+        const int ncq = (ncol + 63) >> 6;
 #pragma unroll
         for (int q = 0; q < W; ++q) {
-            const int x = lane + 64 * q;
-#pragma unroll
-            for (int w = 0; w < W; ++w) srow[q][w] = x < c ? M.rows[x][w] : 0;
-            const int cv = x + 1;
+            const int cv = lane + 64 * q + 1;
             int lo = 0, hi = c;
             while (lo < hi) { int mid = (lo + hi) >> 1; if (M.col[mid] > cv) lo = mid + 1; else hi = mid; }
             const int s0 = lo;
             hi = c;
             while (lo < hi) { int mid = (lo + hi) >> 1; if (M.col[mid] >= cv) lo = mid + 1; else hi = mid; }
-            const int s1 = cv <= ncol ? lo : s0;
-#pragma unroll
-            for (int w = 0; w < W; ++w) {
-                const int a0 = s0 > 64 * w ? s0 : 64 * w, a1 = s1 < 64 * w + 64 ? s1 : 64 * w + 64;
-                uint64_t mk = 0;
-                if (a1 > a0) {
-                    const int len = a1 - a0;
-                    mk = (len == 64 ? ~0ull : ((1ull << len) - 1)) << (a0 - 64 * w);
-                }
-                cls[q][w] = mk;
-            }
+            cs0[q] = s0;
+            cs1[q] = cv <= ncol ? lo : s0;
         }
 
         // Count a node that needs no branching: returns true and sets val, or
@@ -273,7 +264,7 @@ __global__ __launch_bounds__(256) void k_search(SearchArgs a) {
                 if ((P[q] >> lane) & 1) {
                     int d = 0;
 #pragma unroll
-                    for (int w = 0; w < W; ++w) d += popc64(P[w] & srow[q][w]);
+                    for (int w = 0; w < W; ++w) d += popc64(P[w] & M.rows[lane + 64 * q][w]);
                     mn = d < mn ? d : mn;
                     nf += (d == pc - 1);
                     dsum += d;
@@ -306,7 +297,7 @@ __global__ __launch_bounds__(256) void k_search(SearchArgs a) {
                     uint64_t Cz[W];
 #pragma unroll
                     for (int w = 0; w < W; ++w)
-                        Cz[w] = P[w] & (dense ? ~srow[q][w] : srow[q][w]) & upper_mask(z, w);
+                        Cz[w] = P[w] & (dense ? ~M.rows[z][w] : M.rows[z][w]) & upper_mask(z, w);
 #pragma unroll
                     for (int wy = 0; wy < W; ++wy) {
                         while (Cz[wy]) {
@@ -339,19 +330,31 @@ __global__ __launch_bounds__(256) void k_search(SearchArgs a) {
         // the disjoint pairs, T the triangles, P4 the 3-paths, S3 the 3-stars,
         // C4 the 4-cycles, paw, diamond and K4(H) the remaining 4-vertex
         // shapes of H.  All but C(r,4) + C(M,2) is a sum over the vertices,
-        // missing pairs and 2-paths of H, taken by the lanes owning them into
-        // S (12 times its value, so that every term is an integer).  Returns
-        // false, counting nothing, when H is too dense for this to beat
-        // branching on the pairs of R.
+        // missing pairs and 2-paths of H, taken by the lanes holding them
+        // into S (12 times its value, so that every term is an integer).
+        // Returns false, counting nothing, when H is too dense for this to
+        // beat branching on the pairs of R.
         auto k4_missing = [&](const uint64_t (&R)[W], int r, bool whole, int64_t& S, uint64_t& uacc, uint64_t& ops) -> bool {
-            int msum = 0, cm2 = 0, lw = 0;
+            // the vertices of R, packed onto consecutive lanes
+            {
+                int base = 0;
 #pragma unroll
-            for (int q = 0; q < W; ++q) {
-                if ((R[q] >> lane) & 1) {
+                for (int q = 0; q < W; ++q) {
+                    if ((R[q] >> lane) & 1) M.vl[base + popc64(R[q] & lanemask_lt())] = (int16_t)(lane + 64 * q);
+                    base += popc64(R[q]);
+                }
+            }
+            wave_sync();
+            const int rounds = (r + 63) >> 6;
+            int msum = 0, cm2 = 0, lw = 0;
+            for (int t = 0; t < rounds; ++t) {
+                const int j = 64 * t + lane;
+                if (j < r) {
+                    const int v = M.vl[j];
                     int mv = -1;  // R & ~row(v) holds v itself
 #pragma unroll
-                    for (int w = 0; w < W; ++w) mv += popc64(R[w] & ~srow[q][w]);
-                    M.md[lane + 64 * q] = (int16_t)mv;
+                    for (int w = 0; w < W; ++w) mv += popc64(R[w] & ~M.rows[v][w]);
+                    M.md[v] = (int16_t)mv;
                     msum += mv;
                     cm2 += mv * (mv - 1) / 2;
                     lw += mv + mv * (mv - 1) / 2;
@@ -362,17 +365,19 @@ __global__ __launch_bounds__(256) void k_search(SearchArgs a) {
             const int64_t P3 = (int64_t)uni64(pk >> 24);
             // The lanes run in lockstep, so this evaluation takes as long as
             // its busiest lane (missing pairs + 2-paths at the vertices it
-            // owns, ~15 instructions each) plus ~150 for the reductions.  The
+            // holds, ~15 instructions each) plus ~150 for the reductions.  The
             // alternative for one R = P & N+(x) of an l = 5 node is one child
-            // y per lane counting the triangles of R & N+(y): a lane step
-            // (~35 instructions) per vertex of the largest child, ~ r * d,
-            // per 64-vertex chunk of R; for a whole l = 4 node it is that
-            // for every x (~18 instructions a step), ~ |E(R)| * d.
+            // y per lane counting the triangles of R & N+(y): ~35 instructions
+            // per vertex of the largest child, ~ r * d, per 64 children (r of
+            // them here, sharing rounds with the other x through the queue);
+            // for a whole l = 4 node it is that for every x (~18 instructions
+            // a step), ~ |E(R)| * d / 64 rounds of 64 children.
             const int lmax = uniform_i32(wave_max(lw));
             const float pairs = 0.5f * (float)r * (float)(r - 1);
             const float E = pairs - 0.5f * (float)Msum, d = E / pairs;
             const float cost = a.k4_weight * (15.0f * (float)lmax + 150.0f);
-            const float alt = whole ? 18.0f * E * d : 35.0f * (float)r * d * (float)((r + 63) >> 6);
+            const float alt = whole ? 18.0f * E * d * (float)r * d / 64.0f
+                                    : 35.0f * (float)r * d * (float)r / 64.0f;
             if (!(a.k4_weight > 0.f) || cost > alt) return false;
             if (work) ops += (uint64_t)(r + Msum + P3) * W;
             const int64_t Mh = Msum / 2;
@@ -380,13 +385,14 @@ __global__ __launch_bounds__(256) void k_search(SearchArgs a) {
             if (Msum == 0) return true;
             wave_sync();  // md[] of every vertex of R
             const int64_t c2 = (int64_t)(r - 2) * (r - 3) / 2;
-#pragma unroll
-            for (int q = 0; q < W; ++q) {
-                if (!((R[q] >> lane) & 1)) continue;
-                const int v = lane + 64 * q;
+            for (int t = 0; t < rounds; ++t) {
+                const int j = 64 * t + lane;
+                if (j >= r) continue;
+                const int v = M.vl[j];
                 uint64_t hv[W];
 #pragma unroll
-                for (int w = 0; w < W; ++w) hv[w] = R[w] & ~srow[q][w] & (w == q ? ~(1ull << lane) : ~0ull);
+                for (int w = 0; w < W; ++w)
+                    hv[w] = R[w] & ~M.rows[v][w] & (w == (v >> 6) ? ~(1ull << (v & 63)) : ~0ull);
                 const int64_t mv = M.md[v];
                 if (mv == 0) continue;
                 S += -6 * c2 * mv + 12 * (int64_t)(r - 4) * (mv * (mv - 1) / 2) - 2 * mv * (mv - 1) * (mv - 2);
@@ -463,12 +469,25 @@ __global__ __launch_bounds__(256) void k_search(SearchArgs a) {
 
         // children of a node with l = 5 (l = 4), x in [xlo, xhi): the
         // 4-cliques (triangles) of R = P & N+(x) for each x.  A dense R is
-        // counted by the wave from its missing pairs; otherwise lane j of
-        // chunk q takes the child y = 64 q + j.
+        // counted by the wave from its missing pairs; otherwise its children
+        // (x, y) join a queue in LDS and every 64 queued children are counted
+        // one per lane.
         auto children_by_lanes = [&](const uint64_t (&P)[W], int l, int xlo, int xhi) {
             uint64_t lsum = 0, lops = 0, usum = 0;
             int64_t S = 0;
             const int lc = l - 2;
+            int qn = 0;
+            auto run_queue = [&](int cnt) {
+                if (lane < cnt) {
+                    const int e = M.pq[lane];
+                    const int x = e >> 16, y = e & 0xFFFF;
+                    uint64_t Q[W];
+#pragma unroll
+                    for (int w = 0; w < W; ++w) Q[w] = P[w] & M.rows[x][w] & M.rows[y][w] & upper_mask(y, w);
+                    if (lc == 3) lsum += lane_triangles(M, Q, lops);
+                    else lsum += lane_edges(M, Q);
+                }
+            };
             bool done = false;
             if (l == 4 && xlo == 0 && xhi >= c) {
                 const int pc = popcW(P);
@@ -486,24 +505,32 @@ __global__ __launch_bounds__(256) void k_search(SearchArgs a) {
                 xx = nx;
                 uint64_t Rx[W];
 #pragma unroll
-                for (int w = 0; w < W; ++w) Rx[w] = P[w] & M.rows[xx][w] & upper_mask(xx, w);
+                for (int w = 0; w < W; ++w) Rx[w] = uni64(P[w] & M.rows[xx][w] & upper_mask(xx, w));
                 const int rc = popcW(Rx);
                 if (rc < lc + 1) continue;
                 if (work) { wk_nodes += rc; wk_ops += (uint64_t)rc * W; }
                 if (l == 5 && k4_missing(Rx, rc, false, S, usum, lops)) continue;
 #pragma unroll
                 for (int q = 0; q < W; ++q) {
-                    if (Rx[q] == 0) continue;
                     const int y = 64 * q + lane;
                     const bool act = ((Rx[q] >> lane) & 1) && !(rule1 && M.col[y] < l - 1);
-                    if (act) {
-                        uint64_t Q[W];
-#pragma unroll
-                        for (int w = 0; w < W; ++w) Q[w] = Rx[w] & M.rows[y][w] & upper_mask(y, w);
-                        if (lc == 3) lsum += lane_triangles(M, Q, lops);
-                        else lsum += lane_edges(M, Q);
-                    }
+                    const uint64_t bq = ballot(act);
+                    if (act) M.pq[qn + popc64(bq & lanemask_lt())] = (xx << 16) | y;
+                    qn += popc64(bq);
                 }
+                if (qn < 64) continue;
+                wave_sync();
+                while (qn >= 64) {
+                    run_queue(64);
+                    wave_sync();
+                    for (int i = lane; i < qn - 64; i += 64) M.pq[i] = M.pq[64 + i];
+                    qn -= 64;
+                    wave_sync();
+                }
+            }
+            if (qn > 0) {
+                wave_sync();
+                run_queue(qn);
             }
             if (work) wk_ops += wave_sum(lops);
             const int64_t s12 = wave_sum(S);
@@ -564,7 +591,7 @@ __global__ __launch_bounds__(256) void k_search(SearchArgs a) {
                 if (nx < 0 || nx >= xlim || (rule1 && M.col[nx] < l)) { y = -1; break; }
                 x = nx;
 #pragma unroll
-                for (int w = 0; w < W; ++w) R[w] = P[w] & M.rows[x][w] & upper_mask(x, w);
+                for (int w = 0; w < W; ++w) R[w] = uni64(P[w] & M.rows[x][w] & upper_mask(x, w));
             }
             if (y < 0) {  // node exhausted: resume the parent
                 if (sp == 0) break;
@@ -578,7 +605,7 @@ __global__ __launch_bounds__(256) void k_search(SearchArgs a) {
             }
             uint64_t Pc[W];
 #pragma unroll
-            for (int w = 0; w < W; ++w) Pc[w] = R[w] & M.rows[y][w] & upper_mask(y, w);
+            for (int w = 0; w < W; ++w) Pc[w] = uni64(R[w] & M.rows[y][w] & upper_mask(y, w));
             const int lc = l - 2;
             if (work) wk_ops += W;
             if (popcW(Pc) < lc) continue;
@@ -587,10 +614,19 @@ __global__ __launch_bounds__(256) void k_search(SearchArgs a) {
                 int dc = 0;
 #pragma unroll
                 for (int q = 0; q < W; ++q) {
-                    uint64_t hit = 0;
+                    if (q >= ncq) break;
+                    bool hit = false;
 #pragma unroll
-                    for (int w = 0; w < W; ++w) hit |= Pc[w] & cls[q][w];
-                    dc += popc64(ballot(hit != 0));
+                    for (int w = 0; w < W; ++w) {
+                        const int a0 = cs0[q] > 64 * w ? cs0[q] : 64 * w;
+                        const int a1 = cs1[q] < 64 * w + 64 ? cs1[q] : 64 * w + 64;
+                        if (a1 > a0) {
+                            const int len = a1 - a0;
+                            const uint64_t mk = (len == 64 ? ~0ull : ((1ull << len) - 1)) << (a0 - 64 * w);
+                            hit |= (Pc[w] & mk) != 0;
+                        }
+                    }
+                    dc += popc64(ballot(hit));
                 }
                 if (dc < lc) continue;
             }
