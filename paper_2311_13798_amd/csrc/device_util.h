@@ -18,6 +18,43 @@ __device__ __forceinline__ uint64_t uni64(uint64_t x) {
     return ((uint64_t)hi << 32) | lo;
 }
 
+// Wave64 reductions of 32-bit values: DPP moves within each row of 16 lanes
+// (swap neighbours, swap pairs, mirror within 8, mirror within 16), then the
+// four row results read into scalars.  Every lane of the wave must be active.
+template <int CTRL>
+__device__ __forceinline__ int dpp_mov(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+enum : int { DPP_XOR1 = 0xB1, DPP_XOR2 = 0x4E, DPP_HALF_MIRROR = 0x141, DPP_MIRROR = 0x140 };
+
+__device__ __forceinline__ uint32_t wsum_u32(uint32_t v) {
+    int x = (int)v;
+    x += dpp_mov<DPP_XOR1>(x);
+    x += dpp_mov<DPP_XOR2>(x);
+    x += dpp_mov<DPP_HALF_MIRROR>(x);
+    x += dpp_mov<DPP_MIRROR>(x);
+    return (uint32_t)__builtin_amdgcn_readlane(x, 0) + (uint32_t)__builtin_amdgcn_readlane(x, 16) +
+           (uint32_t)__builtin_amdgcn_readlane(x, 32) + (uint32_t)__builtin_amdgcn_readlane(x, 48);
+}
+
+__device__ __forceinline__ int wmax_i32(int x) {
+    x = max(x, dpp_mov<DPP_XOR1>(x));
+    x = max(x, dpp_mov<DPP_XOR2>(x));
+    x = max(x, dpp_mov<DPP_HALF_MIRROR>(x));
+    x = max(x, dpp_mov<DPP_MIRROR>(x));
+    return max(max(__builtin_amdgcn_readlane(x, 0), __builtin_amdgcn_readlane(x, 16)),
+               max(__builtin_amdgcn_readlane(x, 32), __builtin_amdgcn_readlane(x, 48)));
+}
+
+__device__ __forceinline__ int wmin_i32(int x) {
+    x = min(x, dpp_mov<DPP_XOR1>(x));
+    x = min(x, dpp_mov<DPP_XOR2>(x));
+    x = min(x, dpp_mov<DPP_HALF_MIRROR>(x));
+    x = min(x, dpp_mov<DPP_MIRROR>(x));
+    return min(min(__builtin_amdgcn_readlane(x, 0), __builtin_amdgcn_readlane(x, 16)),
+               min(__builtin_amdgcn_readlane(x, 32), __builtin_amdgcn_readlane(x, 48)));
+}
+
 // bits strictly above x within word w of a multi-word row
 __device__ __forceinline__ uint64_t upper_mask(int x, int w) {
     int xw = x >> 6, xb = x & 63;

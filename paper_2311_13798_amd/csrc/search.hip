@@ -273,13 +273,13 @@ __global__ __launch_bounds__(256, (W <= 3 ? 3 : 2)) void k_search(SearchArgs a) 
                 }
             }
             if (work) wk_ops += (uint64_t)pc * W;
-            const uint64_t twoE = wave_sum(dsum);
+            const uint64_t twoE = wsum_u32(dsum);
             if (l == 2) { val = twoE / 2; return true; }
             if (et) {
-                const int mind = wave_min(mn);
+                const int mind = wmin_i32(mn);
                 if (mind >= pc - 1) { val = binom(pc, l); return true; }
                 if (t2 && mind >= pc - 2) {
-                    const int nfull = wave_sum(nf);
+                    const int nfull = (int)wsum_u32((uint32_t)nf);
                     val = twoplex_count(nfull, (pc - nfull) / 2, l);
                     return true;
                 }
@@ -313,9 +313,9 @@ __global__ __launch_bounds__(256, (W <= 3 ? 3 : 2)) void k_search(SearchArgs a) 
                 }
             }
             if (work) wk_ops += (dense ? Mp : twoE / 2) * W;
-            const uint64_t T = wave_sum(t);
+            const uint64_t T = wsum_u32(t);
             if (dense) {
-                const uint64_t S2 = wave_sum(s2);
+                const uint64_t S2 = wsum_u32(s2);
                 val = p64 * (p64 - 1) * (p64 - 2) / 6 - Mp * (p64 - 2) + S2 - T;
             } else {
                 val = T;
@@ -360,9 +360,8 @@ __global__ __launch_bounds__(256, (W <= 3 ? 3 : 2)) void k_search(SearchArgs a) 
                     lw += mv + mv * (mv - 1) / 2;
                 }
             }
-            const uint64_t pk = wave_sum(((uint64_t)cm2 << 24) | (uint64_t)msum);
-            const int Msum = uniform_i32((int)(pk & 0xFFFFFF));
-            const int64_t P3 = (int64_t)uni64(pk >> 24);
+            const int Msum = (int)wsum_u32((uint32_t)msum);
+            const int64_t P3 = (int64_t)wsum_u32((uint32_t)cm2);
             // The lanes run in lockstep, so this evaluation takes as long as
             // its busiest lane (missing pairs + 2-paths at the vertices it
             // holds, ~15 instructions each) plus ~150 for the reductions.  The
@@ -372,7 +371,7 @@ __global__ __launch_bounds__(256, (W <= 3 ? 3 : 2)) void k_search(SearchArgs a) 
             // them here, sharing rounds with the other x through the queue);
             // for a whole l = 4 node it is that for every x (~18 instructions
             // a step), ~ |E(R)| * d / 64 rounds of 64 children.
-            const int lmax = uniform_i32(wave_max(lw));
+            const int lmax = wmax_i32(lw);
             const float pairs = 0.5f * (float)r * (float)(r - 1);
             const float E = pairs - 0.5f * (float)Msum, d = E / pairs;
             const float cost = a.k4_weight * (15.0f * (float)lmax + 150.0f);
@@ -381,7 +380,8 @@ __global__ __launch_bounds__(256, (W <= 3 ? 3 : 2)) void k_search(SearchArgs a) 
             if (!(a.k4_weight > 0.f) || cost > alt) return false;
             if (work) ops += (uint64_t)(r + Msum + P3) * W;
             const int64_t Mh = Msum / 2;
-            uacc += binom(r, 4) + (uint64_t)(Mh * (Mh - 1) / 2);
+            const uint64_t r64 = (uint64_t)r;
+            uacc += r64 * (r64 - 1) * (r64 - 2) * (r64 - 3) / 24 + (uint64_t)(Mh * (Mh - 1) / 2);
             if (Msum == 0) return true;
             wave_sync();  // md[] of every vertex of R
             const int64_t c2 = (int64_t)(r - 2) * (r - 3) / 2;
