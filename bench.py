@@ -2,22 +2,32 @@
 
 One step = the whole hot path over the resident input: ebbkc_prepare on the CSR already in HBM
 (validation, supports, truss-based edge ordering, rank-tagged adjacency) followed by ebbkc_count
-for every k of the workload.  value = k-cliques counted per second = (sum of N_k) / step time.
+for every k of the workload (5, 6, 7, 8, 9; the first count also builds the sub-branch arena).
+value = k-cliques counted per second = (sum over k of N_k) / step time.
 
 Also reported on the same JSON line:
-  roofline      the dominant branch kernel (the widest-work bitmap class at the largest k):
-                algorithmic 64-bit word operations per launch (one AND + popcount of a candidate
-                bitmap word, counted by the library's work counters in a separate instrumented
-                call) divided by that launch's average device time (HIP events on the launch
-                stream, inside the timed region).  Bound: VALU ("alu"); peak derived from
+  roofline      the dominant branch-kernel launch (the bitmap width class launch with the largest
+                device time in the timed step): its algorithmic 64-bit word operations (AND +
+                popcount of one candidate-bitmap word; counted by the library's per-launch work
+                counters, on in the timed run: they cost under 1 %) divided by its device time
+                (HIP events on the launch stream).  Bound: VALU ("alu"); peak derived from
                 256 CUs x 64 int32 lanes/clock x 2.4 GHz = 39.3 T lane-ops/s, four lane-ops per
                 word-op (two 32-bit ANDs, two 32-bit popcounts) -> 9.83 T word-ops/s.
+                traffic: HBM bytes per launch from rocprofv3 FETCH_SIZE + WRITE_SIZE (KiB, scaled
+                by the same counters on a copy kernel of known size) when a committed record
+                for the current kernel source exists, else null.
   cpu_baseline  the CPU oracle (degeneracy-ordered vertex branch and bound) timed on the host
-                cores on a bounded sample of the same workload.
+                cores on a bounded sample of the same workload (the full k = 5 count).
+  batched       many small graphs with per-graph k: one launch per (graph, k) vs the fused
+                batch (one persistent launch per width class, replayed from a HIP graph).
+  served        Poisson request stream against the native continuous-batching server:
+                p50/p99 latency from arrival to result, k-cliques per second, every result
+                equal to the same request run alone.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -28,15 +38,94 @@ sys.path.insert(0, ROOT)
 
 METRIC = "k-cliques counted/sec (R-MAT s18, k=5..9) vs plain kernel; p50/p99 request latency"
 PEAK_WORD_OPS = 256 * 64 * 2.4e9 / 4 / 1e12  # T word-ops/s
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "search_rmat18_k9_traffic.json")
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def search_source_hash():
+    h = hashlib.sha256()
+    for f in ("search.hip", "arena.h", "device_util.h", "common.h"):
+        with open(os.path.join(ROOT, "paper_2311_13798_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def traffic_for(kernel: str, k: int):
+    """HBM bytes per launch of the given kernel at k, from the committed counter record, if it
+    was taken on the current kernel source."""
+    if not os.path.exists(TRAFFIC_RECORD):
+        return None
+    rec = json.load(open(TRAFFIC_RECORD))
+    if rec.get("source_sha256") != search_source_hash():
+        return None
+    e = rec.get("launches", {}).get(f"{kernel}@k={k}")
+    return None if e is None else e.get("hbm_bytes")
+
+
+def systems_forms(ebb, np, torch, configs):
+    """Batched and served forms on graphs shaped like the batched workload (n scaled by 0.1)."""
+    from paper_2311_13798_amd.serve import Server, poisson_requests, summarize
+    params = configs.batch_params(4096)[:512]
+    gs, ks = [], []
+    for p in params:
+        q = dict(p)
+        q["n"] = max(50, int(p["n"] * 0.1))
+        q["clique"] = min(p["clique"], q["n"])
+        gs.append(configs.batch_graph(q))
+        ks.append(int(p["k"]))
+    Gs = [ebb.Graph.from_csr(g) for g in gs]
+    torch.cuda.synchronize()
+    plain = [G.count(k) for G, k in zip(Gs, ks)]  # also builds every arena
+    t = time.perf_counter()
+    plain = [G.count(k) for G, k in zip(Gs, ks)]
+    t_plain = time.perf_counter() - t
+    B = ebb.Batch(Gs, ks)
+    B.run(use_graph=True)
+    t = time.perf_counter()
+    got = B.run(use_graph=True)
+    t_batch = time.perf_counter() - t
+    B.close()
+    tot = sum(plain)
+    batched = {"graphs": len(Gs), "workload": "512 graphs of the batched workload with n scaled by 0.1 "
+                                              "(n U{50..500}, p U[0.005,0.2], 20% with a planted 20..40-clique, "
+                                              "k U{3..10})",
+               "kcliques": tot, "plain_s": round(t_plain, 5), "batched_s": round(t_batch, 5),
+               "plain_kcliques_per_s": tot / t_plain, "batched_kcliques_per_s": tot / t_batch,
+               "vs_plain": round(t_plain / t_batch, 3), "identical": got == plain}
+    log(f"batched: plain {t_plain:.3f}s fused {t_batch:.3f}s identical={got == plain}")
+    # served: the first 128 graphs resident, 2000 Poisson requests with k U{3..10}
+    cat = Gs[:128]
+    alone = {(i, k): G.count(k) for i, G in enumerate(cat) for k in range(3, 11)}
+    served = {"catalogue": len(cat), "requests": 2000, "k": "U{3..10}", "budget_bytes": 1 << 34, "rates": {}}
+    for rate in (200.0, 1000.0, 2000.0):
+        S = Server(cat, 1 << 34)
+        reqs = poisson_requests(rate=rate, count=2000, n_graphs=len(cat), k_lo=3, k_hi=10, seed=1)
+        res = S.run_stream(reqs)
+        st = S.stats()
+        S.close()
+        s = summarize(res)
+        same = all(r["count"] == alone[(g, k)] and r["status"] == 0 for (o, g, k), r in zip(reqs, res))
+        served["rates"][str(int(rate))] = {"p50_ms": round(s["p50_ms"], 4), "p99_ms": round(s["p99_ms"], 4),
+                                           "kcliques_per_s": s["kcliques_per_s"], "epochs": st["epochs"],
+                                           "max_requests_per_epoch": st["max_epoch_requests"],
+                                           "identical_to_alone": same}
+        log(f"served {rate:.0f} req/s: p50 {s['p50_ms']:.3f} ms p99 {s['p99_ms']:.3f} ms identical={same}")
+    for G in Gs:
+        G.close()
+    return batched, served
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--ks", default="5,7", help="comma-separated k values counted in every step")
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=0)
+    ap.add_argument("--ks", default="5,6,7,8,9", help="comma-separated k values counted in every step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-systems", action="store_true", help="skip the batched and served forms")
     ap.add_argument("--cpu-threads", type=int, default=0)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -56,54 +145,53 @@ def main():
     rp = torch.from_numpy(g.row_ptr).cuda()
     ci = torch.from_numpy(g.col_idx).cuda()
     torch.cuda.synchronize()
+    opts = ebb.ebbkc_default_options()
+    opts.count_work = 1
 
-    def step():
-        G = ebb.Graph(rp, ci, g.n)
-        counts, kms = {}, {}
+    def step(tag):
+        G = ebb.Graph(rp, ci, g.n, options=opts)
+        counts, kms, work = {}, {}, {}
         for k in ks:
+            t = time.perf_counter()
             counts[k] = G.count(k)
             kms[k] = G.last_timing()
+            work[k] = [G.last_work_class(W) for W in (1, 2, 3, 4)]
+            log(f"{tag} k={k} N_k={counts[k]} {time.perf_counter() - t:.3f}s")
         prep = G.info.prepare_ms
         info = G.info
         G.close()
-        return counts, kms, prep, info
+        return counts, kms, work, prep, info
 
-    for _ in range(args.warmup):
-        step()
+    for i in range(args.warmup):
+        step(f"warmup {i}")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     runs = []
-    for _ in range(args.steps):
-        runs.append(step())
+    for i in range(args.steps):
+        runs.append(step(f"step {i}"))
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    counts, _, _, info = runs[-1]
+    counts, _, _, _, info = runs[-1]
     total = sum(counts.values())
     ms_per_step = 1000.0 * elapsed / args.steps
 
-    # dominant kernel: the class launch with the largest mean device time
-    kmax = max(ks)
-    per_class = np.mean([np.array(r[1][kmax]) for r in runs], axis=0)
-    wdom = int(np.argmax(per_class)) + 1
-    dom_ms = float(per_class[wdom - 1])
-    # algorithmic work of that launch: instrumented call outside the timed region
-    o = ebb.ebbkc_default_options()
-    o.count_work = 1
-    Gi = ebb.Graph(rp, ci, g.n, options=o)
-    lvl = Gi.export(ebb.ARR_LEVEL)
-    rank = Gi.export(ebb.ARR_RANK)
-    lbr = np.empty_like(lvl)
-    lbr[rank] = lvl
-    lo = int(np.searchsorted(lbr, max(kmax - 2, 64 * (wdom - 1) + 1)))
-    hi = int(np.searchsorted(lbr, 64 * wdom + 1))
-    Gi.count_range(kmax, lo, hi)
-    work = Gi.last_work()
-    Gi.close()
-    achieved = work[2] / (dom_ms / 1e3) / 1e12 if dom_ms > 0 else 0.0
-    roofline = {"bound": "alu", "kernel": f"k_branch<W={wdom}> at k={kmax}", "achieved": round(achieved, 4),
+    # dominant launch: the (k, width class) launch with the largest mean device time
+    best = None
+    for k in ks:
+        per_class = np.mean([np.array(r[1][k]) for r in runs], axis=0)
+        for W in range(1, 5):
+            if best is None or per_class[W - 1] > best[2]:
+                best = (k, W, float(per_class[W - 1]))
+    kd, wd, dom_ms = best
+    word_ops = int(np.mean([r[2][kd][wd - 1][2] for r in runs]))
+    achieved = word_ops / (dom_ms / 1e3) / 1e12 if dom_ms > 0 else 0.0
+    kernel = f"ebb::k_search<{wd}, false>"
+    roofline = {"bound": "alu", "kernel": kernel, "k": kd, "achieved": round(achieved, 4),
                 "peak": round(PEAK_WORD_OPS, 3), "unit": "T word-ops/s", "frac": round(achieved / PEAK_WORD_OPS, 5),
-                "traffic": None, "word_ops_per_launch": work[2], "nodes_per_launch": work[1],
-                "seeds_per_launch": work[0], "launch_ms": round(dom_ms, 3)}
+                "traffic": traffic_for(kernel, kd), "word_ops_per_launch": word_ops,
+                "nodes_per_launch": int(np.mean([r[2][kd][wd - 1][1] for r in runs])),
+                "tasks_per_launch": int(np.mean([r[2][kd][wd - 1][0] for r in runs])),
+                "launch_ms": round(dom_ms, 3)}
 
     line = {
         "metric": METRIC, "value": total / (ms_per_step / 1e3), "unit": "k-cliques/s", "n_gpus": 1,
@@ -114,11 +202,14 @@ def main():
                                ",".join(map(str, ks)),
                    "n": g.n, "m": g.m, "tau": int(info.tau), "peel_rounds": int(info.rounds), "ks": ks},
         "counts": {str(k): v for k, v in counts.items()},
-        "prepare_ms": round(float(np.mean([r[2] for r in runs])), 3),
+        "prepare_ms": round(float(np.mean([r[3] for r in runs])), 3),
         "branch_ms_by_class": {str(k): [round(x, 3) for x in np.mean([np.array(r[1][k]) for r in runs], axis=0)]
                                for k in ks},
         "roofline": roofline,
     }
+
+    if not args.no_systems:
+        line["batched"], line["served"] = systems_forms(ebb, np, torch, configs)
 
     if not args.no_cpu_baseline:
         import oracle
@@ -131,6 +222,7 @@ def main():
                                           "degeneracy-ordered vertex branch and bound, uint64"}
         if 5 in counts:
             line["cpu_baseline"]["agrees_with_gpu_k5"] = n5 == counts[5]
+        log(f"cpu baseline {n5 / dt:.3e} k-cliques/s on {th} threads")
     print(json.dumps(line), flush=True)
 
 

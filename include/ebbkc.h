@@ -164,6 +164,12 @@ ebbkc_status ebbkc_last_timing(const ebbkc_graph *g, double out_ms[4]);
  * one word each), [3] reserved. */
 ebbkc_status ebbkc_last_work(const ebbkc_graph *g, uint64_t out[4]);
 
+/* The same counters for the launch of one bitmap width class
+ * (width_class = W in 1..4: sub-branches of at most 64*W vertices), so that
+ * a launch's work can be set against its time from ebbkc_last_timing.
+ * E_INVALID_ARG for a class outside 1..4. */
+ebbkc_status ebbkc_last_work_class(const ebbkc_graph *g, int32_t width_class, uint64_t out[4]);
+
 void ebbkc_destroy(ebbkc_graph *g);
 
 /* ---- Batched form: many (graph, k) counts in one fused launch.

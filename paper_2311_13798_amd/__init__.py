@@ -48,8 +48,8 @@ class ebbkc_info(ctypes.Structure):
 
 
 EXPORTED = ("ebbkc_default_options", "ebbkc_prepare", "ebbkc_count", "ebbkc_count_range", "ebbkc_count_seeds",
-            "ebbkc_list", "ebbkc_export", "ebbkc_info_get", "ebbkc_last_timing", "ebbkc_last_work", "ebbkc_destroy",
-            "ebbkc_strerror", "ebbkc_batch_create", "ebbkc_batch_run", "ebbkc_batch_tune", "ebbkc_batch_info",
+            "ebbkc_list", "ebbkc_export", "ebbkc_info_get", "ebbkc_last_timing", "ebbkc_last_work",
+            "ebbkc_last_work_class", "ebbkc_destroy", "ebbkc_strerror", "ebbkc_batch_create", "ebbkc_batch_run", "ebbkc_batch_tune", "ebbkc_batch_info",
             "ebbkc_batch_destroy", "ebbkc_server_create", "ebbkc_server_submit", "ebbkc_server_poll",
             "ebbkc_server_stats", "ebbkc_server_destroy")
 
@@ -77,6 +77,7 @@ def load_library(path: str = LIB_PATH):
     lib.ebbkc_info_get.argtypes = [vp, ctypes.POINTER(ebbkc_info)]
     lib.ebbkc_last_timing.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
     lib.ebbkc_last_work.argtypes = [vp, ctypes.POINTER(ctypes.c_uint64)]
+    lib.ebbkc_last_work_class.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_uint64)]
     lib.ebbkc_destroy.argtypes = [vp]
     lib.ebbkc_destroy.restype = None
     lib.ebbkc_batch_create.argtypes = [vp, vp, i32, ctypes.POINTER(ebbkc_options), vp, ctypes.POINTER(vp)]
@@ -98,7 +99,7 @@ def load_library(path: str = LIB_PATH):
     lib.ebbkc_strerror.argtypes = [i32]
     lib.ebbkc_strerror.restype = ctypes.c_char_p
     for f in ("ebbkc_prepare", "ebbkc_count", "ebbkc_count_range", "ebbkc_count_seeds", "ebbkc_list",
-              "ebbkc_export", "ebbkc_info_get", "ebbkc_last_timing", "ebbkc_last_work"):
+              "ebbkc_export", "ebbkc_info_get", "ebbkc_last_timing", "ebbkc_last_work", "ebbkc_last_work_class"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -207,6 +208,12 @@ def ebbkc_last_timing(h):
 def ebbkc_last_work(h):
     out = (ctypes.c_uint64 * 4)()
     _check(load_library().ebbkc_last_work(h, out), "ebbkc_last_work")
+    return [int(x) for x in out]
+
+
+def ebbkc_last_work_class(h, width_class: int):
+    out = (ctypes.c_uint64 * 4)()
+    _check(load_library().ebbkc_last_work_class(h, width_class, out), "ebbkc_last_work_class")
     return [int(x) for x in out]
 
 
@@ -366,6 +373,9 @@ class Graph:
 
     def last_work(self):
         return ebbkc_last_work(self._h)
+
+    def last_work_class(self, width_class: int):
+        return ebbkc_last_work_class(self._h, width_class)
 
     def close(self):
         if getattr(self, "_h", None):

@@ -153,4 +153,10 @@ ebbkc_status ebbkc_last_work(const ebbkc_graph* g, uint64_t out[4]) {
     return EBBKC_OK;
 }
 
+ebbkc_status ebbkc_last_work_class(const ebbkc_graph* g, int32_t width_class, uint64_t out[4]) {
+    if (!g || !out || width_class < 1 || width_class > 4) return EBBKC_E_INVALID_ARG;
+    for (int i = 0; i < 4; ++i) out[i] = g->last_work_class[width_class - 1][i];
+    return EBBKC_OK;
+}
+
 }  // extern "C"

@@ -46,9 +46,10 @@ int opts_of(const ebbkc_options& o) {
     return f;
 }
 
-// counters: [0..4) per-class work counters, [4,5] total lo/hi, [6] error flags,
-// [8..10] search work, [12..16) per-class task counts (task generation)
-constexpr int CNT_WORDS = 16;
+// counters: [0..4) per-class work queues, [4,5] total lo/hi, [6] error flags,
+// [12..16) per-class task counts (task generation), [16 + 4 (W-1) ..) search
+// work of width class W (tasks, nodes, word operations)
+constexpr int CNT_WORDS = 32;
 
 GraphView graph_view(const ebbkc_graph* g) {
     return GraphView{g->rp, g->ci, g->erank, g->rrow, g->orp, g->orow, g->eu, g->ev, g->rank};
@@ -342,7 +343,12 @@ static ebbkc_status read_total(ebbkc_graph* g, uint64_t* out, hipStream_t s) {
     if (err & ERR_DEPTH) return EBBKC_E_K_RANGE;
     if ((err & ERR_OVERFLOW) || g->h_counters[5] != 0) return EBBKC_E_OVERFLOW;
     *out = g->h_counters[4];
-    for (int i = 0; i < 3; ++i) g->last_work[i] = g->h_counters[8 + i];
+    for (int i = 0; i < 4; ++i) g->last_work[i] = 0;
+    for (int W = 1; W <= 4; ++W)
+        for (int i = 0; i < 3; ++i) {
+            g->last_work_class[W - 1][i] = g->h_counters[16 + 4 * (W - 1) + i];
+            g->last_work[i] += g->last_work_class[W - 1][i];
+        }
     return EBBKC_OK;
 }
 
@@ -414,7 +420,7 @@ static ebbkc_status run_tasks(ebbkc_graph* g, int32_t k, const int64_t* tsorted,
         a.k4_weight = k4_weight_of(g->opt.dense_k4);
         a.next = (unsigned long long*)(g->d_counters + W - 1);
         a.total = (unsigned long long*)(g->d_counters + 4);
-        a.work = (unsigned long long*)(g->d_counters + 8);
+        a.work = (unsigned long long*)(g->d_counters + 16 + 4 * (W - 1));
         a.err = (int*)(g->d_counters + 6);
         a.per_task = per_task ? per_task + off : nullptr;
         a.task_off = task_off ? task_off + off : nullptr;
@@ -453,6 +459,8 @@ ebbkc_status count_impl(ebbkc_graph* g, int32_t k, int64_t r_begin, int64_t r_en
     if (r_begin < 0) r_begin = 0;
     for (int i = 0; i < 4; ++i) g->last_ms[i] = 0.0;
     for (int i = 0; i < 4; ++i) g->last_work[i] = 0;
+    for (int W = 0; W < 4; ++W)
+        for (int i = 0; i < 4; ++i) g->last_work_class[W][i] = 0;
     CHKH(hipMemsetAsync(g->d_counters, 0, CNT_WORDS * sizeof(uint64_t), s));
     unsigned long long* total = (unsigned long long*)(g->d_counters + 4);
     if (k == 3) {  // sum of |V(g_i)| over the seeds

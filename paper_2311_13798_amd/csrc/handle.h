@@ -61,6 +61,7 @@ struct ebbkc_graph {
     uint64_t* h_counters = nullptr;   // pinned mirror
     double last_ms[4] = {0, 0, 0, 0};
     uint64_t last_work[4] = {0, 0, 0, 0};
+    uint64_t last_work_class[4][4] = {};
     int64_t device_bytes = 0;
 };
 

@@ -334,7 +334,7 @@ __global__ __launch_bounds__(256, (W <= 3 ? 3 : 2)) void k_search(SearchArgs a) 
         // into S (12 times its value, so that every term is an integer).
         // Returns false, counting nothing, when H is too dense for this to
         // beat branching on the pairs of R.
-        auto k4_missing = [&](const uint64_t (&R)[W], int r, bool whole, int64_t& S, uint64_t& uacc, uint64_t& ops) -> bool {
+        auto k4_missing = [&](const uint64_t (&R)[W], int r, bool whole, int64_t& S, uint64_t& uacc) -> bool {
             // the vertices of R, packed onto consecutive lanes
             {
                 int base = 0;
@@ -378,7 +378,7 @@ __global__ __launch_bounds__(256, (W <= 3 ? 3 : 2)) void k_search(SearchArgs a) 
             const float alt = whole ? 18.0f * E * d * (float)r * d / 64.0f
                                     : 35.0f * (float)r * d * (float)r / 64.0f;
             if (!(a.k4_weight > 0.f) || cost > alt) return false;
-            if (work) ops += (uint64_t)(r + Msum + P3) * W;
+            if (work) wk_ops += (uint64_t)(r + Msum + P3) * W;
             const int64_t Mh = Msum / 2;
             const uint64_t r64 = (uint64_t)r;
             uacc += r64 * (r64 - 1) * (r64 - 2) * (r64 - 3) / 24 + (uint64_t)(Mh * (Mh - 1) / 2);
@@ -491,7 +491,7 @@ __global__ __launch_bounds__(256, (W <= 3 ? 3 : 2)) void k_search(SearchArgs a) 
             bool done = false;
             if (l == 4 && xlo == 0 && xhi >= c) {
                 const int pc = popcW(P);
-                done = pc < 4 || k4_missing(P, pc, true, S, usum, lops);
+                done = pc < 4 || k4_missing(P, pc, true, S, usum);
             }
             int xx = xlo - 1;
             while (!done) {
@@ -509,7 +509,7 @@ __global__ __launch_bounds__(256, (W <= 3 ? 3 : 2)) void k_search(SearchArgs a) 
                 const int rc = popcW(Rx);
                 if (rc < lc + 1) continue;
                 if (work) { wk_nodes += rc; wk_ops += (uint64_t)rc * W; }
-                if (l == 5 && k4_missing(Rx, rc, false, S, usum, lops)) continue;
+                if (l == 5 && k4_missing(Rx, rc, false, S, usum)) continue;
 #pragma unroll
                 for (int q = 0; q < W; ++q) {
                     const int y = 64 * q + lane;
