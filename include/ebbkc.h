@@ -227,16 +227,31 @@ typedef struct {
     double done_ms;     /* result available */
 } ebbkc_result;
 
-/* graphs: the catalogue (handles must outlive the server and not be used
- * elsewhere while it runs).  Builds the sub-branch arenas up front. */
+/* graphs: the catalogue of n prepared handles on the current device (they
+ * must outlive the server and not be used elsewhere while it runs); opt as
+ * for ebbkc_batch_create (NULL: defaults).  budget_bytes > 0 bounds the
+ * estimated device footprint of one epoch: per request 16 bytes per seed task
+ * plus, for each of the 4096 waves a persistent launch can keep resident, one
+ * bitmap of (tau+2)^2 bits (a sub-branch has at most tau vertices, Section
+ * 4.2).  Builds the sub-branch arenas up front and starts the worker thread.
+ * E_INVALID_ARG for a NULL handle, n <= 0 or budget_bytes <= 0; E_OOM / E_HIP
+ * when an arena or the stream cannot be created.  The counts are the
+ * k-clique counts of Section 2, as ebbkc_count gives them. */
 ebbkc_status ebbkc_server_create(ebbkc_graph *const *graphs, int32_t n, const ebbkc_options *opt,
                                  int64_t budget_bytes, ebbkc_server **out);
+/* Queue a request for the count of k-cliques (k >= 1) of catalogue graph
+ * `graph`; *out_id identifies its result.  Never blocks on the device.
+ * E_INVALID_ARG for a graph index outside the catalogue or k < 1. */
 ebbkc_status ebbkc_server_submit(ebbkc_server *s, int32_t graph, int32_t k, int64_t *out_id);
-/* Move up to max completed results to out (*n_out of them); wait = 1 blocks
- * until at least one is available or nothing is pending. */
+/* Move up to max completed results to out (*n_out of them, in completion
+ * order; the caller owns out, max entries); wait = 1 blocks until at least
+ * one is available or nothing is pending.  A failed request is a result with
+ * its status set and count 0. */
 ebbkc_status ebbkc_server_poll(ebbkc_server *s, ebbkc_result *out, int32_t max, int32_t wait, int32_t *n_out);
 /* [requests submitted, epochs run, most requests in one epoch, requests waiting or running] */
 ebbkc_status ebbkc_server_stats(const ebbkc_server *s, int64_t out[4]);
+/* Finishes the requests already submitted, stops the worker and frees the
+ * server (not the catalogue's handles). */
 void ebbkc_server_destroy(ebbkc_server *s);
 
 const char *ebbkc_strerror(ebbkc_status s);

@@ -1,6 +1,6 @@
 """Writes the stored expected values under tests/golden/ by calling the CPU oracle only.
 
-Usage:  python tests/golden/make_golden.py [--with-k7]
+Usage:  python tests/golden/make_golden.py [--with-k7] [--with-k12] [--only NAME]
 Every value written here comes from ``oracle`` applied to the seeded inputs of ``graphgen``.
 """
 import argparse
@@ -62,6 +62,7 @@ def graph_record(g, ks, list_ks=(), sample_ks=(), nsample=0, seed=0):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--with-k7", action="store_true")
+    ap.add_argument("--with-k12", action="store_true")
     ap.add_argument("--only", default="")
     args = ap.parse_args()
     if args.only in ("", "er_small"):
@@ -73,6 +74,12 @@ def main():
         ks = [1, 2, 3, 4, 5, 6] + ([7] if args.with_k7 else [])
         rec = graph_record(g, ks=ks, sample_ks=((5, 1000), (7, 100), (9, 70)), nsample=300, seed=1)
         json.dump(rec, open(os.path.join(OUT, "rmat18.json"), "w"), indent=1)
+    if args.only in ("", "cl1m"):
+        # Chung-Lu n = 10^6 with 200 planted cliques (the dense-branch early-termination workload)
+        g = configs.cl_planted()
+        ks = [1, 2, 3, 4, 5, 8, 10] + ([12] if args.with_k12 else [])
+        rec = graph_record(g, ks=ks, sample_ks=((8, 200), (10, 200), (12, 200)), nsample=300, seed=3)
+        json.dump(rec, open(os.path.join(OUT, "cl1m.json"), "w"), indent=1)
 
 
 if __name__ == "__main__":
