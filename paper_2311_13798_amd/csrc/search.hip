@@ -99,13 +99,16 @@ struct Frame {
     int32_t x, l, y, pad;
 };
 
+// children queued per node before the lanes count them (room for one more x)
+constexpr int QRUN = 256, QCAP = QRUN + 256;
+
 template <int W>
 struct SearchMem {
     uint64_t rows[64 * W][W];
     int16_t col[64 * W];
     int16_t md[64 * W];      // missing pairs per vertex inside the set being counted
     int16_t vl[64 * W];      // that set's vertices in order, one per lane
-    int32_t pq[64 + 64 * W];  // queued children x << 16 | y of the node being counted
+    int32_t pq[2][QCAP];     // queued children |Q| << 16 | x << 8 | y (and a sort buffer)
     Frame<W> fr[LDS_FRAMES];
 };
 
@@ -477,16 +480,51 @@ __global__ __launch_bounds__(256, (W <= 3 ? 3 : 2)) void k_search(SearchArgs a) 
             int64_t S = 0;
             const int lc = l - 2;
             int qn = 0;
-            auto run_queue = [&](int cnt) {
+            // Count the queued children [base, base + cnt), cnt <= 64, one per lane.
+            auto run_queue = [&](const int32_t* q, int base, int cnt) {
                 if (lane < cnt) {
-                    const int e = M.pq[lane];
-                    const int x = e >> 16, y = e & 0xFFFF;
+                    const int e = q[base + lane];
+                    const int x = (e >> 8) & 0xFF, y = e & 0xFF;
                     uint64_t Q[W];
 #pragma unroll
                     for (int w = 0; w < W; ++w) Q[w] = P[w] & M.rows[x][w] & M.rows[y][w] & upper_mask(y, w);
                     if (lc == 3) lsum += lane_triangles(M, Q, lops);
                     else lsum += lane_edges(M, Q);
                 }
+            };
+            // Count every queued child: a lane's work grows with |Q|, so the
+            // queue is first sorted by |Q| (stable LSD passes over |Q| >> 3,
+            // ballot partitions) and counted 64 at a time in that order.
+            auto drain = [&]() {
+                wave_sync();
+                int cur = 0;
+                if (qn > 64) {
+                    for (int b = 19; b < 24; ++b) {
+                        const int32_t* src = M.pq[cur];
+                        int32_t* dst = M.pq[cur ^ 1];
+                        int nz = 0;
+                        for (int i0 = 0; i0 < qn; i0 += 64) {
+                            const int i = i0 + lane;
+                            nz += popc64(ballot(i < qn && !((src[i] >> b) & 1)));
+                        }
+                        int z0 = 0, o0 = nz;
+                        for (int i0 = 0; i0 < qn; i0 += 64) {
+                            const int i = i0 + lane;
+                            const bool valid = i < qn;
+                            const int e = valid ? src[i] : 0;
+                            const bool one = valid && ((e >> b) & 1);
+                            const uint64_t bo = ballot(one), bz = ballot(valid && !one);
+                            if (valid) dst[one ? o0 + popc64(bo & lanemask_lt()) : z0 + popc64(bz & lanemask_lt())] = e;
+                            z0 += popc64(bz);
+                            o0 += popc64(bo);
+                        }
+                        wave_sync();
+                        cur ^= 1;
+                    }
+                }
+                for (int i0 = 0; i0 < qn; i0 += 64) run_queue(M.pq[cur], i0, qn - i0 < 64 ? qn - i0 : 64);
+                qn = 0;
+                wave_sync();
             };
             bool done = false;
             if (l == 4 && xlo == 0 && xhi >= c) {
@@ -515,23 +553,17 @@ __global__ __launch_bounds__(256, (W <= 3 ? 3 : 2)) void k_search(SearchArgs a) 
                     const int y = 64 * q + lane;
                     const bool act = ((Rx[q] >> lane) & 1) && !(rule1 && M.col[y] < l - 1);
                     const uint64_t bq = ballot(act);
-                    if (act) M.pq[qn + popc64(bq & lanemask_lt())] = (xx << 16) | y;
+                    if (act) {
+                        int qy = 0;  // |Q| of the child (x, y)
+#pragma unroll
+                        for (int w = 0; w < W; ++w) qy += popc64(Rx[w] & M.rows[y][w] & upper_mask(y, w));
+                        M.pq[0][qn + popc64(bq & lanemask_lt())] = (qy << 16) | (xx << 8) | y;
+                    }
                     qn += popc64(bq);
                 }
-                if (qn < 64) continue;
-                wave_sync();
-                while (qn >= 64) {
-                    run_queue(64);
-                    wave_sync();
-                    for (int i = lane; i < qn - 64; i += 64) M.pq[i] = M.pq[64 + i];
-                    qn -= 64;
-                    wave_sync();
-                }
+                if (qn >= QRUN) drain();
             }
-            if (qn > 0) {
-                wave_sync();
-                run_queue(qn);
-            }
+            if (qn > 0) drain();
             if (work) wk_ops += wave_sum(lops);
             const int64_t s12 = wave_sum(S);
             tacc.add((uint64_t)((int64_t)(wave_sum(lsum) + usum) + s12 / 12));
