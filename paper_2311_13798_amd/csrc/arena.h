@@ -65,6 +65,38 @@ __host__ __device__ inline int64_t task_slot(int64_t t) { return t >> 20; }
 __host__ __device__ inline int task_x0(int64_t t) { return (int)((t >> 10) & 1023); }
 __host__ __device__ inline int task_x1(int64_t t) { return (int)(t & 1023); }
 
+// The root tasks of a slot with c vertices at l0 = k-2 (needs c >= l0): one
+// task [0, c) unless the root's work bound log C(c, l0) exceeds the split
+// threshold; then ranges [x0, x1) of first root vertices.  Root vertex x heads
+// at most C(c-1-x, l0-1) cliques; consecutive vertices are grouped until their
+// bound reaches that of x = 0, so no task is heavier than the heaviest single
+// vertex and light vertices do not each reload the slot.  Calls emit(x0, x1)
+// for every task and returns their number.
+__device__ inline double log_binom(int n, int r) {
+    return lgamma((double)n + 1) - lgamma((double)r + 1) - lgamma((double)(n - r) + 1);
+}
+template <class F>
+__device__ inline int root_tasks(int c, int l0, double log_threshold, F&& emit) {
+    if (l0 < 4 || c < l0 + 8 || log_binom(c, l0) <= log_threshold) {
+        emit(0, c);
+        return 1;
+    }
+    const double top = log_binom(c - 1, l0 - 1);
+    const int last = c - l0;
+    int n = 0, x0 = 0;
+    double acc = 0.0;
+    for (int x = 0; x <= last; ++x) {
+        acc += exp(log_binom(c - 1 - x, l0 - 1) - top);
+        if (acc >= 0.999 || x == last) {
+            emit(x0, x + 1);
+            ++n;
+            x0 = x + 1;
+            acc = 0.0;
+        }
+    }
+    return n;
+}
+
 struct SearchArgs {
     ArenaView A;
     const int64_t* tasks;

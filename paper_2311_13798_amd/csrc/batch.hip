@@ -77,19 +77,11 @@ inline unsigned gridn(int64_t n) {
     return (unsigned)b;
 }
 
-__device__ __forceinline__ bool split_root_b(int c, int l0, double log_threshold) {
-    if (l0 < 4 || c < l0 + 8) return false;
-    const double lc = lgamma((double)c + 1) - lgamma((double)l0 + 1) - lgamma((double)(c - l0) + 1);
-    return lc > log_threshold;
-}
-
 __global__ void k_btask_counts(const int32_t* __restrict__ seed_c, int64_t n, int l0, double log_thr,
                                int32_t* __restrict__ tcount) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         const int c = seed_c[i];
-        int t = 0;
-        if (c >= l0) t = split_root_b(c, l0, log_thr) ? c - l0 + 1 : 1;
-        tcount[i] = t;
+        tcount[i] = c >= l0 ? root_tasks(c, l0, log_thr, [](int, int) {}) : 0;
     }
 }
 
@@ -101,19 +93,14 @@ __global__ void k_btask_fill(const int32_t* __restrict__ seed_c, int64_t n, int 
         if (c < l0) continue;
         const int W = width_of(c);
         int64_t o = base + toff[i];
-        if (split_root_b(c, l0, log_thr)) {
-            for (int x = 0; x <= c - l0; ++x, ++o) {
-                tasks[o] = task_pack(i, x, x + 1);
-                tgraph[o] = graph;
-                keys[o] = ((uint64_t)(W - 1) << 8) | (uint64_t)(255 - (c - 1 - x));
-                vals[o] = (uint32_t)o;
-            }
-        } else {
-            tasks[o] = task_pack(i, 0, c);
+        root_tasks(c, l0, log_thr, [&](int x0, int x1) {
+            tasks[o] = task_pack(i, x0, x1);
             tgraph[o] = graph;
-            keys[o] = ((uint64_t)(W - 1) << 8) | (uint64_t)(255 - (c > 255 ? 255 : c));
+            const int usable = x0 == 0 && x1 >= c ? c : c - 1 - x0;
+            keys[o] = ((uint64_t)(W - 1) << 8) | (uint64_t)(255 - (usable > 255 ? 255 : usable));
             vals[o] = (uint32_t)o;
-        }
+            ++o;
+        });
     }
 }
 

@@ -102,20 +102,11 @@ __global__ void k_class_fill(const int32_t* __restrict__ flag, const int64_t* __
         if (flag[s]) list[pos[s]] = (int32_t)s;
 }
 
-// is the root of a slot with c vertices split at l0 = k-2?  (log C(c, l0) > log threshold)
-__device__ __forceinline__ bool split_root(int c, int l0, double log_threshold) {
-    if (l0 < 4 || c < l0 + 8) return false;
-    const double lc = lgamma((double)c + 1) - lgamma((double)l0 + 1) - lgamma((double)(c - l0) + 1);
-    return lc > log_threshold;
-}
-
 __global__ void k_task_counts(const int32_t* __restrict__ seed_c, int64_t i0, int64_t n, int l0, double log_thr,
                               int32_t* __restrict__ tcount) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         const int c = seed_c[i0 + i];
-        int t = 0;
-        if (c >= l0) t = split_root(c, l0, log_thr) ? c - l0 + 1 : 1;
-        tcount[i] = t;
+        tcount[i] = c >= l0 ? root_tasks(c, l0, log_thr, [](int, int) {}) : 0;
     }
 }
 
@@ -127,19 +118,15 @@ __global__ void k_task_fill(const int32_t* __restrict__ seed_c, int64_t i0, int6
         if (c < l0) continue;
         const int W = width_of(c);
         int64_t o = toff[i];
-        if (split_root(c, l0, log_thr)) {
-            for (int x = 0; x <= c - l0; ++x, ++o) {
-                tasks[o] = task_pack(i0 + i, x, x + 1);
-                keys[o] = ((uint64_t)(W - 1) << 8) | (uint64_t)(255 - (c - 1 - x));
-                vals[o] = (uint32_t)o;
-            }
-            atomicAdd(&cls_count[W - 1], (unsigned long long)(c - l0 + 1));
-        } else {
-            tasks[o] = task_pack(i0 + i, 0, c);
-            keys[o] = ((uint64_t)(W - 1) << 8) | (uint64_t)(255 - (c > 255 ? 255 : c));
+        const int nt = root_tasks(c, l0, log_thr, [&](int x0, int x1) {
+            tasks[o] = task_pack(i0 + i, x0, x1);
+            // heaviest first: more vertices after the first one of the range
+            const int usable = x0 == 0 && x1 >= c ? c : c - 1 - x0;
+            keys[o] = ((uint64_t)(W - 1) << 8) | (uint64_t)(255 - (usable > 255 ? 255 : usable));
             vals[o] = (uint32_t)o;
-            atomicAdd(&cls_count[W - 1], 1ull);
-        }
+            ++o;
+        });
+        atomicAdd(&cls_count[W - 1], (unsigned long long)nt);
     }
 }
 
