@@ -399,8 +399,11 @@ __global__ __launch_bounds__(256, (W <= 3 ? 3 : 2)) void k_search(SearchArgs a) 
                 const int64_t mv = M.md[v];
                 if (mv == 0) continue;
                 S += -6 * c2 * mv + 12 * (int64_t)(r - 4) * (mv * (mv - 1) / 2) - 2 * mv * (mv - 1) * (mv - 2);
-                int64_t t2 = 0;
-                // missing pairs v-u: codegree in H, triangles, diamonds, 3-paths, K4(H)
+                // missing pairs v-u: codegree cc in H (triangles, diamonds,
+                // paws), the 3-paths through v-u, K4(H).  Per-v sums in 32 bits:
+                // t2 = sum cc over all u; over u > v: a1 = sum cc, a2 = sum cc^2,
+                // a3 = sum (m_u - 1)
+                int32_t t2 = 0, a1 = 0, a2 = 0, a3 = 0;
 #pragma unroll
                 for (int wu = 0; wu < W; ++wu) {
                     uint64_t bu = hv[wu];
@@ -415,9 +418,9 @@ __global__ __launch_bounds__(256, (W <= 3 ? 3 : 2)) void k_search(SearchArgs a) 
                         for (int w = 0; w < W; ++w) cc += popc64(hv[w] & hu[w]);
                         t2 += cc;
                         if (u > v) {
-                            const int64_t mu = M.md[u];
-                            S += -4 * (int64_t)(r - 3) * cc + 12 * (cc - (mu - 1) * (mv - 1)) -
-                                 6 * (int64_t)cc * (cc - 1);
+                            a1 += cc;
+                            a2 += cc * cc;
+                            a3 += M.md[u] - 1;
                             if (cc >= 2) {
                                 uint64_t X[W];
 #pragma unroll
@@ -438,8 +441,12 @@ __global__ __launch_bounds__(256, (W <= 3 ? 3 : 2)) void k_search(SearchArgs a) 
                         }
                     }
                 }
-                S += 6 * t2 * (mv - 2);
-                // 2-paths a-v-b (a < b): 4 C4 = sum (codeg(a,b) - 1)
+                // per missing pair: 12 (cc - (m_u-1)(m_v-1)) - 4 (r-3) cc - 6 cc (cc-1)
+                S += (int64_t)(18 - 4 * (r - 3)) * a1 - 6 * (int64_t)a2 - 12 * (mv - 1) * (int64_t)a3 +
+                     6 * (int64_t)t2 * (mv - 2);
+                // 2-paths a-v-b (a < b): 4 C4 = sum (codeg(a,b) - 1); with
+                // ha = R & ~row(a), |ha & ~row(b)| = codeg(a,b) + 2 [a-b missing]
+                int32_t wsum = 0;
 #pragma unroll
                 for (int wa = 0; wa < W; ++wa) {
                     uint64_t ba = hv[wa];
@@ -447,25 +454,27 @@ __global__ __launch_bounds__(256, (W <= 3 ? 3 : 2)) void k_search(SearchArgs a) 
                         const int a0 = wa * 64 + __builtin_ctzll(ba);
                         ba &= ba - 1;
                         uint64_t ha[W], rest[W];
+                        int corr = 0;
 #pragma unroll
                         for (int w = 0; w < W; ++w) {
                             ha[w] = R[w] & ~M.rows[a0][w];
                             rest[w] = hv[w] & upper_mask(a0, w);
+                            corr += 2 * popc64(rest[w] & ha[w]) + popc64(rest[w]);
                         }
+                        wsum -= corr;
 #pragma unroll
                         for (int wb = 0; wb < W; ++wb) {
                             if (wb < wa) continue;
                             while (rest[wb]) {
                                 const int b = wb * 64 + __builtin_ctzll(rest[wb]);
                                 rest[wb] &= rest[wb] - 1;
-                                int cd = (ha[wb] >> (b & 63)) & 1 ? -3 : -1;  // a, b themselves when a-b is missing
 #pragma unroll
-                                for (int w = 0; w < W; ++w) cd += popc64(ha[w] & ~M.rows[b][w]);
-                                S += 3 * cd;
+                                for (int w = 0; w < W; ++w) wsum += popc64(ha[w] & ~M.rows[b][w]);
                             }
                         }
                     }
                 }
+                S += 3 * (int64_t)wsum;
             }
             return true;
         };
