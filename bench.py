@@ -20,9 +20,9 @@ Also reported on the same JSON line:
                 cores on a bounded sample of the same workload (the full k = 5 count).
   batched       many small graphs with per-graph k: one launch per (graph, k) vs the fused
                 batch (one persistent launch per width class, replayed from a HIP graph).
-  served        Poisson request stream against the native continuous-batching server:
-                p50/p99 latency from arrival to result, k-cliques per second, every result
-                equal to the same request run alone.
+  served        Poisson request streams (50, 200, 1000 requests/s) over a mixed resident catalogue
+                against the native continuous-batching server: p50/p99 latency from arrival to
+                result, k-cliques per second, every result equal to the same request run alone.
 """
 from __future__ import annotations
 
@@ -96,23 +96,32 @@ def systems_forms(ebb, np, torch, configs):
                "plain_kcliques_per_s": tot / t_plain, "batched_kcliques_per_s": tot / t_batch,
                "vs_plain": round(t_plain / t_batch, 3), "identical": got == plain}
     log(f"batched: plain {t_plain:.3f}s fused {t_batch:.3f}s identical={got == plain}")
-    # served: the first 128 graphs resident, 2000 Poisson requests with k U{3..10}
-    cat = Gs[:128]
-    alone = {(i, k): G.count(k) for i, G in enumerate(cat) for k in range(3, 11)}
-    served = {"catalogue": len(cat), "requests": 2000, "k": "U{3..10}", "budget_bytes": 1 << 34, "rates": {}}
-    for rate in (200.0, 1000.0, 2000.0):
+    # served: a mixed catalogue resident (R-MAT s12, s13, Chung-Lu 1e4..3e5, ER(2000, 0.01) and 64 of
+    # the batched graphs), Poisson requests with k U{3..12}; R-MAT s13 at k = 12 takes ~2.3 s alone
+    named = [("rmat12", configs.rmat_scale(12)), ("rmat13", configs.rmat_scale(13)),
+             ("cl1e4", configs.cl_planted(10000)), ("cl3e4", configs.cl_planted(30000)),
+             ("cl1e5", configs.cl_planted(100000)), ("cl3e5", configs.cl_planted(300000)),
+             ("er2000", configs.er_small())]
+    extra = [ebb.Graph.from_csr(g) for _, g in named]
+    cat = extra + Gs[:64]
+    alone = {(i, k): G.count(k) for i, G in enumerate(cat) for k in range(3, 13)}
+    served = {"catalogue": [n for n, _ in named] + ["64 batched-workload graphs (n scaled by 0.1)"],
+              "k": "U{3..12}", "budget_bytes": 1 << 34, "epochs_in_flight": 3, "rates": {}}
+    for rate, count in ((50.0, 500), (200.0, 1000), (1000.0, 2000)):
         S = Server(cat, 1 << 34)
-        reqs = poisson_requests(rate=rate, count=2000, n_graphs=len(cat), k_lo=3, k_hi=10, seed=1)
+        reqs = poisson_requests(rate=rate, count=count, n_graphs=len(cat), k_lo=3, k_hi=12, seed=1)
         res = S.run_stream(reqs)
         st = S.stats()
         S.close()
         s = summarize(res)
         same = all(r["count"] == alone[(g, k)] and r["status"] == 0 for (o, g, k), r in zip(reqs, res))
-        served["rates"][str(int(rate))] = {"p50_ms": round(s["p50_ms"], 4), "p99_ms": round(s["p99_ms"], 4),
-                                           "kcliques_per_s": s["kcliques_per_s"], "epochs": st["epochs"],
-                                           "max_requests_per_epoch": st["max_epoch_requests"],
+        served["rates"][str(int(rate))] = {"requests": count, "p50_ms": round(s["p50_ms"], 4),
+                                           "p99_ms": round(s["p99_ms"], 4), "kcliques_per_s": s["kcliques_per_s"],
+                                           "epochs": st["epochs"], "max_requests_per_epoch": st["max_epoch_requests"],
                                            "identical_to_alone": same}
         log(f"served {rate:.0f} req/s: p50 {s['p50_ms']:.3f} ms p99 {s['p99_ms']:.3f} ms identical={same}")
+    for G in extra:
+        G.close()
     for G in Gs:
         G.close()
     return batched, served

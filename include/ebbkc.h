@@ -70,7 +70,9 @@ typedef struct {
     int32_t rule1;             /* 1 (default): colour pruning Rule (1), Section 4.3 */
     int32_t rule2;             /* 1 (default): colour pruning Rule (2), Section 4.3 */
     int32_t waves_per_block;   /* workgroup size in wavefronts (default 4) */
-    int32_t blocks_per_cu;     /* persistent workgroups per compute unit (0 = auto) */
+    int32_t blocks_per_cu;     /* persistent workgroups per compute unit (0 = auto; -1 = one
+                                  workgroup per four tasks, not persistent, so that launches on
+                                  other streams share the compute units) */
     int32_t split_threshold;   /* root-branch work above which a seed is split (0 = auto, <0 = never) */
     int32_t count_work;        /* 1: record search work counters (ebbkc_last_work); default 0 */
     int32_t dense_k4;          /* 4-cliques of a dense candidate set counted from its missing pairs
@@ -195,7 +197,7 @@ ebbkc_status ebbkc_batch_create(ebbkc_graph *const *graphs, const int32_t *ks, i
 ebbkc_status ebbkc_batch_run(ebbkc_batch *b, int32_t use_graph, uint64_t *out_counts, void *stream);
 
 /* Autotuner: times the batch under split thresholds {2^16, 2^22, 2^28, never}
- * x workgroups per CU {auto, 1, 2}, checks every setting gives the same
+ * x workgroups per CU {auto, 1, 2, not persistent}, checks every setting gives the same
  * counts, keeps the fastest (also in the process cache and, if the
  * environment names one, the EBBKC_TUNE_CACHE file). */
 ebbkc_status ebbkc_batch_tune(ebbkc_batch *b, void *stream, int32_t *out_split, int32_t *out_blocks_per_cu);
@@ -207,13 +209,16 @@ void ebbkc_batch_destroy(ebbkc_batch *b);
 
 /* ---- Served form: continuous batching of count requests.
  * A catalogue of prepared graphs stays resident in device memory; requests
- * (graph index, k) are submitted as they arrive.  A worker thread runs
- * epochs: each takes the waiting requests in arrival order while their
- * estimated device footprint fits budget_bytes (a request larger than the
- * budget runs alone) and counts them all in one fused batched launch;
- * requests arriving meanwhile join the next epoch.  Results are exact and do
- * not depend on which requests share an epoch.  Times are milliseconds since
- * the server was created (host steady clock). */
+ * (graph index, k) are submitted as they arrive.  A worker thread keeps up to
+ * three epochs in flight, each on its own stream: an epoch takes the waiting
+ * requests in arrival order while the estimated footprint of all epochs in
+ * flight fits budget_bytes (a request larger than the budget runs when
+ * nothing else does) and counts them in one fused batched launch per width
+ * class.  The launches are not persistent, so epochs share the compute units
+ * and requests arriving while a long epoch runs start at once in another
+ * slot.  Results are exact and do not depend on which requests share an
+ * epoch.  Times are milliseconds since the server was created (host steady
+ * clock). */
 typedef struct ebbkc_server ebbkc_server;
 
 typedef struct {

@@ -54,6 +54,11 @@ struct ebbkc_batch {
     hipGraphExec_t exec = nullptr;
     bool dirty = true;  // tasks changed since capture
     double last_ms = 0.0;
+    // device memory: stream-ordered on mem_stream when async_mem (the served
+    // form, whose epochs overlap: a plain free would wait for the device)
+    bool async_mem = false;
+    hipStream_t mem_stream = nullptr;
+    bool own_host = true;  // h_tot / h_ctr allocated by the batch
 };
 
 namespace ebb {
@@ -137,10 +142,19 @@ int opts_of(const ebbkc_options& o) {
     return f;
 }
 
+hipError_t dev_alloc(const ebbkc_batch* b, void** p, size_t bytes, hipStream_t s) {
+    return b->async_mem ? hipMallocAsync(p, bytes, s) : hipMalloc(p, bytes);
+}
+void dev_free(const ebbkc_batch* b, void* p, hipStream_t s) {
+    if (!p) return;
+    if (b->async_mem) (void)hipFreeAsync(p, s);
+    else (void)hipFree(p);
+}
+
 void free_tasks(ebbkc_batch* b) {
-    if (b->tasks) (void)hipFree(b->tasks);
-    if (b->tgraph) (void)hipFree(b->tgraph);
-    if (b->gframes) (void)hipFree(b->gframes);
+    dev_free(b, b->tasks, b->mem_stream);
+    dev_free(b, b->tgraph, b->mem_stream);
+    dev_free(b, b->gframes, b->mem_stream);
     b->tasks = nullptr;
     b->tgraph = nullptr;
     b->gframes = nullptr;
@@ -161,8 +175,8 @@ ebbkc_status build_tasks(ebbkc_batch* b, hipStream_t s) {
     for (int i = 0; i < n; ++i) nsmax = std::max(nsmax, b->graphs[(size_t)i]->nseeds);
     int32_t* tc = nullptr;
     int64_t* tmp = nullptr;
-    CHKB(hipMalloc((void**)&tc, sizeof(int32_t) * (nsmax + 1)));
-    CHKB(hipMalloc((void**)&tmp, sizeof(int64_t) * (scan_tmp_elems(nsmax + 1) + 64)));
+    CHKB(dev_alloc(b, (void**)&tc, sizeof(int32_t) * (nsmax + 1), s));
+    CHKB(dev_alloc(b, (void**)&tmp, sizeof(int64_t) * (scan_tmp_elems(nsmax + 1) + 64), s));
     std::vector<int64_t> tcount((size_t)n, 0);
     for (int i = 0; i < n; ++i) {
         ebbkc_graph* g = b->graphs[(size_t)i];
@@ -170,15 +184,15 @@ ebbkc_status build_tasks(ebbkc_batch* b, hipStream_t s) {
         if (k < 3 || g->nseeds == 0) continue;
         const int64_t ns = g->nseeds;
         int64_t* to = nullptr;
-        CHKB(hipMalloc((void**)&to, sizeof(int64_t) * (ns + 1)));
+        CHKB(dev_alloc(b, (void**)&to, sizeof(int64_t) * (ns + 1), s));
         hipLaunchKernelGGL(k_btask_counts, dim3(gridn(ns)), dim3(256), 0, s, g->seed_c, ns, k - 2, log_thr, tc);
         CHKB(exclusive_scan_i32(tc, to, ns, to + ns, tmp, s));
         CHKB(hipMemcpyAsync(&tcount[(size_t)i], to + ns, sizeof(int64_t), hipMemcpyDeviceToHost, s));
         toffs[(size_t)i] = to;
     }
     CHKB(hipStreamSynchronize(s));
-    (void)hipFree(tc);
-    (void)hipFree(tmp);
+    dev_free(b, tc, s);
+    dev_free(b, tmp, s);
     for (int i = 0; i < n; ++i) {
         gbase[(size_t)i] = total;
         total += tcount[(size_t)i];
@@ -186,7 +200,7 @@ ebbkc_status build_tasks(ebbkc_batch* b, hipStream_t s) {
     gbase[(size_t)n] = total;
     b->ntasks = total;
     if (total == 0) {
-        for (auto p : toffs) if (p) (void)hipFree(p);
+        for (auto p : toffs) dev_free(b, p, s);
         return EBBKC_OK;
     }
     if (total >= ((int64_t)1 << 32)) return EBBKC_E_OOM;
@@ -195,14 +209,14 @@ ebbkc_status build_tasks(ebbkc_batch* b, hipStream_t s) {
     uint64_t *keys = nullptr, *keys2 = nullptr;
     uint32_t *vals = nullptr, *vals2 = nullptr;
     const int64_t hn = radix_hist_elems(total);
-    CHKB(hipMalloc((void**)&tasks, sizeof(int64_t) * total));
-    CHKB(hipMalloc((void**)&tg, sizeof(int32_t) * total));
-    CHKB(hipMalloc((void**)&keys, sizeof(uint64_t) * total));
-    CHKB(hipMalloc((void**)&keys2, sizeof(uint64_t) * total));
-    CHKB(hipMalloc((void**)&vals, sizeof(uint32_t) * total));
-    CHKB(hipMalloc((void**)&vals2, sizeof(uint32_t) * total));
-    CHKB(hipMalloc((void**)&hist, sizeof(int64_t) * hn));
-    CHKB(hipMalloc((void**)&htmp, sizeof(int64_t) * (scan_tmp_elems(hn) + 64)));
+    CHKB(dev_alloc(b, (void**)&tasks, sizeof(int64_t) * total, s));
+    CHKB(dev_alloc(b, (void**)&tg, sizeof(int32_t) * total, s));
+    CHKB(dev_alloc(b, (void**)&keys, sizeof(uint64_t) * total, s));
+    CHKB(dev_alloc(b, (void**)&keys2, sizeof(uint64_t) * total, s));
+    CHKB(dev_alloc(b, (void**)&vals, sizeof(uint32_t) * total, s));
+    CHKB(dev_alloc(b, (void**)&vals2, sizeof(uint32_t) * total, s));
+    CHKB(dev_alloc(b, (void**)&hist, sizeof(int64_t) * hn, s));
+    CHKB(dev_alloc(b, (void**)&htmp, sizeof(int64_t) * (scan_tmp_elems(hn) + 64), s));
     for (int i = 0; i < n; ++i) {
         if (!toffs[(size_t)i]) continue;
         ebbkc_graph* g = b->graphs[(size_t)i];
@@ -211,8 +225,8 @@ ebbkc_status build_tasks(ebbkc_batch* b, hipStream_t s) {
                            keys, vals);
     }
     CHKB(radix_sort_u64(keys, vals, keys2, vals2, total, 10, hist, htmp, s));
-    CHKB(hipMalloc((void**)&b->tasks, sizeof(int64_t) * total));
-    CHKB(hipMalloc((void**)&b->tgraph, sizeof(int32_t) * total));
+    CHKB(dev_alloc(b, (void**)&b->tasks, sizeof(int64_t) * total, s));
+    CHKB(dev_alloc(b, (void**)&b->tgraph, sizeof(int32_t) * total, s));
     hipLaunchKernelGGL(k_bgather, dim3(gridn(total)), dim3(256), 0, s, tasks, tg, vals, total, b->tasks, b->tgraph);
     CHKB(hipMemsetAsync(b->ctr, 0, 16 * sizeof(unsigned long long), s));
     hipLaunchKernelGGL(k_bclass_hist, dim3(gridn(total)), dim3(256), 0, s, keys, total, b->ctr);
@@ -220,15 +234,15 @@ ebbkc_status build_tasks(ebbkc_batch* b, hipStream_t s) {
     CHKB(hipMemcpyAsync(cc, b->ctr, sizeof(cc), hipMemcpyDeviceToHost, s));
     CHKB(hipStreamSynchronize(s));
     for (int w = 0; w < 4; ++w) b->ccount[w] = cc[w];
-    for (auto p : toffs) if (p) (void)hipFree(p);
+    for (auto p : toffs) dev_free(b, p, s);
     void* ptrs[] = {tasks, tg, keys, keys2, vals, vals2, hist, htmp};
-    for (void* p : ptrs) (void)hipFree(p);
+    for (void* p : ptrs) dev_free(b, p, s);
     // frames for deep searches
     if (b->kmax > 2 + 2 * LDS_FRAMES + 4) {
         int64_t waves = 0;
         for (int W = 1; W <= MAX_W; ++W)
             waves = std::max(waves, search_grid_waves(W, false, total, b->cu_count, b->opt.blocks_per_cu));
-        CHKB(hipMalloc(&b->gframes, (size_t)waves * GLOBAL_FRAMES * search_frame_bytes(MAX_W)));
+        CHKB(dev_alloc(b, &b->gframes, (size_t)waves * GLOBAL_FRAMES * search_frame_bytes(MAX_W), s));
     }
     b->dirty = true;
     return EBBKC_OK;
@@ -349,23 +363,42 @@ void save_cache_file() {
 }  // namespace
 }  // namespace ebb
 
-using namespace ebb;
+namespace ebb {
+namespace {
 
-extern "C" {
+void batch_destroy_impl(ebbkc_batch* b) {
+    if (!b) return;
+    free_tasks(b);
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    void* ptrs[] = {b->views, b->gk, b->gtot, b->ctr};
+    for (void* p : ptrs) dev_free(b, p, b->mem_stream);
+    if (b->own_host) {
+        if (b->h_tot) (void)hipHostFree(b->h_tot);
+        if (b->h_ctr) (void)hipHostFree(b->h_ctr);
+    }
+    delete b;
+}
 
-ebbkc_status ebbkc_batch_create(ebbkc_graph* const* graphs, const int32_t* ks, int32_t n, const ebbkc_options* opt,
-                                void* stream, ebbkc_batch** out) {
-    if (!graphs || !ks || n <= 0 || !out) return EBBKC_E_INVALID_ARG;
-    hipStream_t s = (hipStream_t)stream;
+// Batch of n (graph, k) counts.  async_mem: device memory is stream-ordered on
+// s; h_tot / h_ctr: caller-owned pinned result buffers (2 n and 16 words), or
+// null to allocate them.  use_cache: take a cached tuning choice when opt is
+// null.
+ebbkc_status batch_create_impl(ebbkc_graph* const* graphs, const int32_t* ks, int32_t n, const ebbkc_options* opt,
+                               hipStream_t s, bool async_mem, unsigned long long* h_tot, unsigned long long* h_ctr,
+                               ebbkc_batch** out) {
     ebbkc_batch* b = new ebbkc_batch();
+    b->async_mem = async_mem;
+    b->mem_stream = s;
     b->graphs.assign(graphs, graphs + n);
     b->ks.assign(ks, ks + n);
     if (opt) b->opt = *opt; else ebbkc_default_options(&b->opt);
     b->opt.count_work = 0;
     (void)hipGetDevice(&b->device);
-    hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, b->device) != hipSuccess) { delete b; return EBBKC_E_HIP; }
-    b->cu_count = prop.multiProcessorCount;
+    if (hipDeviceGetAttribute(&b->cu_count, hipDeviceAttributeMultiprocessorCount, b->device) != hipSuccess) {
+        delete b;
+        return EBBKC_E_HIP;
+    }
     std::vector<ArenaView> views((size_t)n);
     for (int i = 0; i < n; ++i) {
         ebbkc_graph* g = graphs[i];
@@ -382,20 +415,26 @@ ebbkc_status ebbkc_batch_create(ebbkc_graph* const* graphs, const int32_t* ks, i
     for (int i = 0; i < n; ++i)
         if (kk[(size_t)i] >= 3 && kk[(size_t)i] - 2 > graphs[i]->tau) kk[(size_t)i] = 0;
     b->ks = kk;
-    auto fail = [&](ebbkc_status st) { ebbkc_batch_destroy(b); return st; };
-    if (hipMalloc((void**)&b->views, sizeof(ArenaView) * n) != hipSuccess) return fail(EBBKC_E_OOM);
-    if (hipMalloc((void**)&b->gk, sizeof(int32_t) * n) != hipSuccess) return fail(EBBKC_E_OOM);
-    if (hipMalloc((void**)&b->gtot, sizeof(unsigned long long) * 2 * n) != hipSuccess) return fail(EBBKC_E_OOM);
-    if (hipMalloc((void**)&b->ctr, sizeof(unsigned long long) * 16) != hipSuccess) return fail(EBBKC_E_OOM);
-    if (hipHostMalloc((void**)&b->h_tot, sizeof(unsigned long long) * 2 * n, hipHostMallocDefault) != hipSuccess)
-        return fail(EBBKC_E_OOM);
-    if (hipHostMalloc((void**)&b->h_ctr, sizeof(unsigned long long) * 16, hipHostMallocDefault) != hipSuccess)
-        return fail(EBBKC_E_OOM);
+    auto fail = [&](ebbkc_status st) { batch_destroy_impl(b); return st; };
+    if (dev_alloc(b, (void**)&b->views, sizeof(ArenaView) * n, s) != hipSuccess) return fail(EBBKC_E_OOM);
+    if (dev_alloc(b, (void**)&b->gk, sizeof(int32_t) * n, s) != hipSuccess) return fail(EBBKC_E_OOM);
+    if (dev_alloc(b, (void**)&b->gtot, sizeof(unsigned long long) * 2 * n, s) != hipSuccess) return fail(EBBKC_E_OOM);
+    if (dev_alloc(b, (void**)&b->ctr, sizeof(unsigned long long) * 16, s) != hipSuccess) return fail(EBBKC_E_OOM);
+    if (h_tot && h_ctr) {
+        b->own_host = false;
+        b->h_tot = h_tot;
+        b->h_ctr = h_ctr;
+    } else {
+        if (hipHostMalloc((void**)&b->h_tot, sizeof(unsigned long long) * 2 * n, hipHostMallocDefault) != hipSuccess)
+            return fail(EBBKC_E_OOM);
+        if (hipHostMalloc((void**)&b->h_ctr, sizeof(unsigned long long) * 16, hipHostMallocDefault) != hipSuccess)
+            return fail(EBBKC_E_OOM);
+    }
     if (hipMemcpyAsync(b->views, views.data(), sizeof(ArenaView) * n, hipMemcpyHostToDevice, s) != hipSuccess ||
         hipMemcpyAsync(b->gk, b->ks.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s) != hipSuccess)
         return fail(EBBKC_E_HIP);
     if (ensure_tables(b->device, s) != hipSuccess) return fail(EBBKC_E_HIP);
-    {
+    if (!async_mem) {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         if (g_tune_cache.empty()) load_cache_file();
         auto it = g_tune_cache.find(signature(b));
@@ -408,6 +447,19 @@ ebbkc_status ebbkc_batch_create(ebbkc_graph* const* graphs, const int32_t* ks, i
     if (st) return fail(st);
     *out = b;
     return EBBKC_OK;
+}
+
+}  // namespace
+}  // namespace ebb
+
+using namespace ebb;
+
+extern "C" {
+
+ebbkc_status ebbkc_batch_create(ebbkc_graph* const* graphs, const int32_t* ks, int32_t n, const ebbkc_options* opt,
+                                void* stream, ebbkc_batch** out) {
+    if (!graphs || !ks || n <= 0 || !out) return EBBKC_E_INVALID_ARG;
+    return batch_create_impl(graphs, ks, n, opt, (hipStream_t)stream, false, nullptr, nullptr, out);
 }
 
 ebbkc_status ebbkc_batch_run(ebbkc_batch* b, int32_t use_graph, uint64_t* out_counts, void* stream) {
@@ -433,7 +485,7 @@ ebbkc_status ebbkc_batch_tune(ebbkc_batch* b, void* stream, int32_t* out_split, 
     if (!b) return EBBKC_E_INVALID_ARG;
     hipStream_t s = (hipStream_t)stream;
     const int32_t splits[] = {1 << 16, 1 << 22, 1 << 28, -1};
-    const int32_t bpcs[] = {0, 1, 2};
+    const int32_t bpcs[] = {0, 1, 2, -1};
     double best = 1e300;
     int32_t bs = b->opt.split_threshold, bb = b->opt.blocks_per_cu;
     std::vector<uint64_t> ref(b->graphs.size()), cur(b->graphs.size());
@@ -472,49 +524,57 @@ ebbkc_status ebbkc_batch_info(const ebbkc_batch* b, int64_t* out_tasks, double* 
     return EBBKC_OK;
 }
 
-void ebbkc_batch_destroy(ebbkc_batch* b) {
-    if (!b) return;
-    free_tasks(b);
-    if (b->exec) (void)hipGraphExecDestroy(b->exec);
-    if (b->graph) (void)hipGraphDestroy(b->graph);
-    void* ptrs[] = {b->views, b->gk, b->gtot, b->ctr};
-    for (void* p : ptrs) if (p) (void)hipFree(p);
-    if (b->h_tot) (void)hipHostFree(b->h_tot);
-    if (b->h_ctr) (void)hipHostFree(b->h_ctr);
-    delete b;
-}
+void ebbkc_batch_destroy(ebbkc_batch* b) { batch_destroy_impl(b); }
 
 }  // extern "C"
 
 // ============================================================== served form
 //
 // A catalogue of prepared graphs stays resident; requests (graph, k) are
-// submitted as they arrive and a worker thread runs them in epochs: every
-// epoch takes the waiting requests in arrival order while their estimated
-// device footprint fits the budget (a request larger than the budget runs
-// alone), merges their task lists and runs one fused launch per width class.
-// Requests arriving while an epoch runs join the next one.  Footprint of a
-// request: 16 bytes per task (task word, graph id, sort key) plus, for each
-// resident wave, one c x c bitmap of the graph's largest sub-branch
-// (~tau^2 bits per live branch).
+// submitted as they arrive.  A worker thread keeps up to SLOTS epochs in
+// flight, each on its own stream: an epoch takes waiting requests in arrival
+// order while the estimated device footprint of all epochs in flight fits the
+// budget (a request larger than the budget runs when nothing else does),
+// merges their task lists and enqueues one launch per width class.  Launches
+// are not persistent (one workgroup per four tasks), so epochs on different
+// streams share the compute units as workgroups retire: requests arriving
+// while a long epoch runs start at once in another slot instead of waiting
+// for it.  Device memory of an epoch is stream-ordered, so starting and
+// retiring epochs never waits for the device.  Footprint of a request: 16
+// bytes per task (task word, graph id, sort key) plus, for each resident wave,
+// one c x c bitmap of the graph's largest sub-branch (~tau^2 bits per live
+// branch).
 
 #include <condition_variable>
 #include <deque>
 #include <thread>
+
+namespace {
+constexpr int SLOTS = 3;
+constexpr int SLOT_REQUESTS = 4096;  // most requests in one epoch
+}  // namespace
 
 struct ebbkc_server {
     std::vector<ebbkc_graph*> cat;
     std::vector<int64_t> branch_bytes;  // per graph: tau^2 / 8 bytes
     ebbkc_options opt{};
     int64_t budget = 0;
-    hipStream_t stream = nullptr;
+    struct Slot {
+        hipStream_t stream = nullptr;
+        hipEvent_t done = nullptr;
+        ebbkc_batch* batch = nullptr;
+        std::vector<ebbkc_result> reqs;
+        int64_t bytes = 0;
+        unsigned long long* h_tot = nullptr;  // pinned, 2 * SLOT_REQUESTS
+        unsigned long long* h_ctr = nullptr;  // pinned, 16
+    } slots[SLOTS];
     std::thread worker;
     std::mutex mu;
     std::condition_variable cv, done_cv;
     bool stop = false;
     std::deque<ebbkc_result> pending;
     std::vector<ebbkc_result> done;
-    int64_t next_id = 0, in_flight = 0, epochs = 0, max_epoch_requests = 0;
+    int64_t next_id = 0, in_flight = 0, epochs = 0, max_epoch_requests = 0, in_flight_bytes = 0;
     std::chrono::steady_clock::time_point t0;
     double now_ms() const {
         return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -526,28 +586,76 @@ namespace {
 
 int64_t request_bytes(const ebbkc_server* S, const ebbkc_result& r) {
     const ebbkc_graph* g = S->cat[(size_t)r.graph];
-    const int64_t waves = 4096;  // resident waves of a persistent launch (upper bound)
+    const int64_t waves = 4096;  // resident waves of a launch (upper bound)
     return 16 * (g->nseeds + 1) + waves * S->branch_bytes[(size_t)r.graph];
+}
+
+// Finish the epoch of slot sl (its event has completed): results to done.
+void retire(ebbkc_server* S, ebbkc_server::Slot& sl) {
+    std::vector<uint64_t> cnt(sl.reqs.size(), 0);
+    const ebbkc_status st = finish(sl.batch, cnt.data());
+    batch_destroy_impl(sl.batch);
+    sl.batch = nullptr;
+    const double t_done = S->now_ms();
+    std::lock_guard<std::mutex> lk(S->mu);
+    for (size_t i = 0; i < sl.reqs.size(); ++i) {
+        ebbkc_result r = sl.reqs[i];
+        r.status = st;
+        r.count = st ? 0 : cnt[i];
+        r.done_ms = t_done;
+        S->done.push_back(r);
+    }
+    S->in_flight -= (int64_t)sl.reqs.size();
+    S->in_flight_bytes -= sl.bytes;
+    S->epochs++;
+    sl.reqs.clear();
+    sl.bytes = 0;
 }
 
 void serve_loop(ebbkc_server* S) {
     (void)hipSetDevice(S->cat.empty() ? 0 : S->cat[0]->device);
     for (;;) {
+        bool progressed = false;
+        for (auto& sl : S->slots) {
+            if (sl.batch && hipEventQuery(sl.done) == hipSuccess) {
+                retire(S, sl);
+                progressed = true;
+            }
+        }
+        if (progressed) S->done_cv.notify_all();
+        // admit waiting requests into a free slot
+        ebbkc_server::Slot* free_slot = nullptr;
+        int busy = 0;
+        for (auto& sl : S->slots) {
+            if (sl.batch) ++busy;
+            else if (!free_slot) free_slot = &sl;
+        }
         std::vector<ebbkc_result> epoch;
+        int64_t bytes = 0;
         {
             std::unique_lock<std::mutex> lk(S->mu);
-            S->cv.wait(lk, [&] { return S->stop || !S->pending.empty(); });
-            if (S->stop && S->pending.empty()) return;
-            int64_t used = 0;
-            while (!S->pending.empty()) {
-                const int64_t need = request_bytes(S, S->pending.front());
-                if (!epoch.empty() && used + need > S->budget) break;
-                used += need;
-                epoch.push_back(S->pending.front());
-                S->pending.pop_front();
+            if (S->stop && S->pending.empty() && busy == 0) return;
+            if (free_slot) {
+                while (!S->pending.empty() && (int)epoch.size() < SLOT_REQUESTS) {
+                    const int64_t need = request_bytes(S, S->pending.front());
+                    const bool alone = epoch.empty() && busy == 0;
+                    if (!alone && S->in_flight_bytes + bytes + need > S->budget) break;
+                    bytes += need;
+                    epoch.push_back(S->pending.front());
+                    S->pending.pop_front();
+                }
+                S->in_flight += (int64_t)epoch.size();
+                S->in_flight_bytes += bytes;
+                S->max_epoch_requests = std::max<int64_t>(S->max_epoch_requests, (int64_t)epoch.size());
             }
-            S->in_flight = (int64_t)epoch.size();
+            if (epoch.empty() && !progressed) {
+                // nothing to start: wait for a submission, or poll the epochs in flight
+                if (busy == 0) S->cv.wait(lk, [&] { return S->stop || !S->pending.empty(); });
+                else S->cv.wait_for(lk, std::chrono::microseconds(50));
+                continue;
+            }
         }
+        if (epoch.empty()) continue;
         const double t_admit = S->now_ms();
         std::vector<ebbkc_graph*> gs;
         std::vector<int32_t> ks;
@@ -556,26 +664,52 @@ void serve_loop(ebbkc_server* S) {
             gs.push_back(S->cat[(size_t)r.graph]);
             ks.push_back(r.k);
         }
+        ebbkc_server::Slot& sl = *free_slot;
+        sl.reqs = epoch;
+        sl.bytes = bytes;
+        ebbkc_options o = S->opt;
+        int kmax = 0;
+        for (int k : ks) kmax = std::max(kmax, k);
+        if (kmax <= 2 + 2 * LDS_FRAMES + 4) o.blocks_per_cu = -1;  // share the device with the other slots
         ebbkc_batch* b = nullptr;
-        std::vector<uint64_t> cnt(epoch.size(), 0);
-        ebbkc_status st = ebbkc_batch_create(gs.data(), ks.data(), (int32_t)gs.size(), &S->opt, S->stream, &b);
-        if (!st) st = ebbkc_batch_run(b, 0, cnt.data(), S->stream);
-        if (b) ebbkc_batch_destroy(b);
-        const double t_done = S->now_ms();
-        {
-            std::lock_guard<std::mutex> lk(S->mu);
-            for (size_t i = 0; i < epoch.size(); ++i) {
-                epoch[i].status = st;
-                epoch[i].count = st ? 0 : cnt[i];
-                epoch[i].done_ms = t_done;
-                S->done.push_back(epoch[i]);
+        ebbkc_status st = batch_create_impl(gs.data(), ks.data(), (int32_t)gs.size(), &o, sl.stream, true, sl.h_tot,
+                                            sl.h_ctr, &b);
+        if (!st) st = enqueue(b, sl.stream);
+        if (!st && hipEventRecord(sl.done, sl.stream) != hipSuccess) st = EBBKC_E_HIP;
+        if (st) {  // the epoch fails as a whole; its requests report the status
+            if (b) {
+                (void)hipStreamSynchronize(sl.stream);
+                batch_destroy_impl(b);
             }
-            S->in_flight = 0;
+            const double t_done = S->now_ms();
+            std::lock_guard<std::mutex> lk(S->mu);
+            for (auto& r : sl.reqs) {
+                r.status = st;
+                r.count = 0;
+                r.done_ms = t_done;
+                S->done.push_back(r);
+            }
+            S->in_flight -= (int64_t)sl.reqs.size();
+            S->in_flight_bytes -= sl.bytes;
             S->epochs++;
-            S->max_epoch_requests = std::max<int64_t>(S->max_epoch_requests, (int64_t)epoch.size());
+            sl.reqs.clear();
+            sl.bytes = 0;
+            S->done_cv.notify_all();
+            continue;
         }
-        S->done_cv.notify_all();
+        sl.batch = b;
     }
+}
+
+void server_free(ebbkc_server* S) {
+    for (auto& sl : S->slots) {
+        if (sl.stream) (void)hipStreamSynchronize(sl.stream);
+        if (sl.done) (void)hipEventDestroy(sl.done);
+        if (sl.stream) (void)hipStreamDestroy(sl.stream);
+        if (sl.h_tot) (void)hipHostFree(sl.h_tot);
+        if (sl.h_ctr) (void)hipHostFree(sl.h_ctr);
+    }
+    delete S;
 }
 
 }  // namespace
@@ -589,6 +723,7 @@ ebbkc_status ebbkc_server_create(ebbkc_graph* const* graphs, int32_t n, const eb
     ebbkc_server* S = new ebbkc_server();
     S->cat.assign(graphs, graphs + n);
     if (opt) S->opt = *opt; else ebbkc_default_options(&S->opt);
+    S->opt.count_work = 0;
     S->budget = budget_bytes;
     for (int i = 0; i < n; ++i) {
         if (!graphs[i]) { delete S; return EBBKC_E_INVALID_ARG; }
@@ -599,7 +734,17 @@ ebbkc_status ebbkc_server_create(ebbkc_graph* const* graphs, int32_t n, const eb
             if (st) { delete S; return st; }
         }
     }
-    if (hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking) != hipSuccess) { delete S; return EBBKC_E_HIP; }
+    if (ebb::ensure_tables(graphs[0]->device, nullptr) != hipSuccess) { delete S; return EBBKC_E_HIP; }
+    for (auto& sl : S->slots) {
+        if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess ||
+            hipHostMalloc((void**)&sl.h_tot, sizeof(unsigned long long) * 2 * SLOT_REQUESTS, hipHostMallocDefault) !=
+                hipSuccess ||
+            hipHostMalloc((void**)&sl.h_ctr, sizeof(unsigned long long) * 16, hipHostMallocDefault) != hipSuccess) {
+            ebb::server_free(S);
+            return EBBKC_E_HIP;
+        }
+    }
     S->t0 = std::chrono::steady_clock::now();
     S->worker = std::thread(ebb::serve_loop, S);
     *out = S;
@@ -652,8 +797,7 @@ void ebbkc_server_destroy(ebbkc_server* S) {
     }
     S->cv.notify_all();
     if (S->worker.joinable()) S->worker.join();
-    if (S->stream) (void)hipStreamDestroy(S->stream);
-    delete S;
+    ebb::server_free(S);
 }
 
 }  // extern "C"
