@@ -70,9 +70,9 @@ typedef struct {
     int32_t rule1;             /* 1 (default): colour pruning Rule (1), Section 4.3 */
     int32_t rule2;             /* 1 (default): colour pruning Rule (2), Section 4.3 */
     int32_t waves_per_block;   /* workgroup size in wavefronts (default 4) */
-    int32_t blocks_per_cu;     /* persistent workgroups per compute unit (0 = auto; -1 = one
-                                  workgroup per four tasks, not persistent, so that launches on
-                                  other streams share the compute units) */
+    int32_t blocks_per_cu;     /* persistent workgroups per compute unit (0 = as many as fit;
+                                  -1 = one workgroup per four tasks, not persistent; -2 = one fewer
+                                  than fit, so launches on other streams always find room) */
     int32_t split_threshold;   /* root-branch work above which a seed is split (0 = auto, <0 = never) */
     int32_t count_work;        /* 1: record search work counters (ebbkc_last_work); default 0 */
     int32_t dense_k4;          /* 4-cliques of a dense candidate set counted from its missing pairs
@@ -214,9 +214,8 @@ void ebbkc_batch_destroy(ebbkc_batch *b);
  * requests in arrival order while the estimated footprint of all epochs in
  * flight fits budget_bytes (a request larger than the budget runs when
  * nothing else does) and counts them in one fused batched launch per width
- * class.  The launches are not persistent, so epochs share the compute units
- * and requests arriving while a long epoch runs start at once in another
- * slot.  Results are exact and do not depend on which requests share an
+ * class.  Each launch leaves one workgroup slot per compute unit free, so
+ * requests arriving while a long epoch runs start at once in another slot.  Results are exact and do not depend on which requests share an
  * epoch.  Times are milliseconds since the server was created (host steady
  * clock). */
 typedef struct ebbkc_server ebbkc_server;

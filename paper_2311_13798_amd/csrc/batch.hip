@@ -535,11 +535,10 @@ void ebbkc_batch_destroy(ebbkc_batch* b) { batch_destroy_impl(b); }
 // flight, each on its own stream: an epoch takes waiting requests in arrival
 // order while the estimated device footprint of all epochs in flight fits the
 // budget (a request larger than the budget runs when nothing else does),
-// merges their task lists and enqueues one launch per width class.  Launches
-// are not persistent (one workgroup per four tasks), so epochs on different
-// streams share the compute units as workgroups retire: requests arriving
-// while a long epoch runs start at once in another slot instead of waiting
-// for it.  Device memory of an epoch is stream-ordered, so starting and
+// merges their task lists and enqueues one launch per width class.  Each
+// launch keeps one workgroup per compute unit fewer than fit, so an epoch
+// started on another stream always finds room: requests arriving while a long
+// epoch runs start at once in another slot instead of waiting for it.  Device memory of an epoch is stream-ordered, so starting and
 // retiring epochs never waits for the device.  Footprint of a request: 16
 // bytes per task (task word, graph id, sort key) plus, for each resident wave,
 // one c x c bitmap of the graph's largest sub-branch (~tau^2 bits per live
@@ -550,8 +549,9 @@ void ebbkc_batch_destroy(ebbkc_batch* b) { batch_destroy_impl(b); }
 #include <thread>
 
 namespace {
-constexpr int SLOTS = 3;
+constexpr int SLOTS = 3;             // the last one takes light requests only
 constexpr int SLOT_REQUESTS = 4096;  // most requests in one epoch
+constexpr double HEAVY_BOUND = 3e11; // work bound above which a request is heavy
 }  // namespace
 
 struct ebbkc_server {
@@ -572,8 +572,13 @@ struct ebbkc_server {
     std::mutex mu;
     std::condition_variable cv, done_cv;
     bool stop = false;
-    std::deque<ebbkc_result> pending;
+    struct Pending {
+        ebbkc_result r;
+        bool heavy;
+    };
+    std::deque<Pending> pending;
     std::vector<ebbkc_result> done;
+    std::vector<std::vector<int64_t>> chist;  // per graph: seeds by |V(g_i)| (0..256)
     int64_t next_id = 0, in_flight = 0, epochs = 0, max_epoch_requests = 0, in_flight_bytes = 0;
     std::chrono::steady_clock::time_point t0;
     double now_ms() const {
@@ -588,6 +593,19 @@ int64_t request_bytes(const ebbkc_server* S, const ebbkc_result& r) {
     const ebbkc_graph* g = S->cat[(size_t)r.graph];
     const int64_t waves = 4096;  // resident waves of a launch (upper bound)
     return 16 * (g->nseeds + 1) + waves * S->branch_bytes[(size_t)r.graph];
+}
+
+// Bound on the search of request (graph, k): sum over the seeds of
+// C(|V(g_i)|, k-2), the (k-2)-subsets a root could extend.  Loose (closed
+// forms end dense branches early) but it separates the requests that run for
+// seconds from those that take a millisecond.
+bool is_heavy(const ebbkc_server* S, int32_t graph, int32_t k) {
+    if (k < 5) return false;
+    const std::vector<int64_t>& h = S->chist[(size_t)graph];
+    double b = 0.0;
+    for (int c = k - 2; c < (int)h.size(); ++c)
+        if (h[(size_t)c]) b += (double)h[(size_t)c] * std::exp(std::lgamma(c + 1.0) - std::lgamma(k - 1.0) - std::lgamma(c - k + 3.0));
+    return b > HEAVY_BOUND;
 }
 
 // Finish the epoch of slot sl (its event has completed): results to done.
@@ -623,81 +641,94 @@ void serve_loop(ebbkc_server* S) {
             }
         }
         if (progressed) S->done_cv.notify_all();
-        // admit waiting requests into a free slot
-        ebbkc_server::Slot* free_slot = nullptr;
+        // admit waiting requests: every free slot takes the requests of one
+        // class (heavy or light, the class of the oldest waiting request; the
+        // last slot light only) in arrival order while the footprint of the
+        // epochs in flight fits the budget
         int busy = 0;
-        for (auto& sl : S->slots) {
-            if (sl.batch) ++busy;
-            else if (!free_slot) free_slot = &sl;
-        }
-        std::vector<ebbkc_result> epoch;
-        int64_t bytes = 0;
+        for (auto& sl : S->slots) busy += sl.batch != nullptr;
+        struct Start {
+            ebbkc_server::Slot* slot;
+            std::vector<ebbkc_result> reqs;
+            int64_t bytes;
+        };
+        std::vector<Start> starts;
         {
             std::unique_lock<std::mutex> lk(S->mu);
             if (S->stop && S->pending.empty() && busy == 0) return;
-            if (free_slot) {
-                while (!S->pending.empty() && (int)epoch.size() < SLOT_REQUESTS) {
-                    const int64_t need = request_bytes(S, S->pending.front());
-                    const bool alone = epoch.empty() && busy == 0;
-                    if (!alone && S->in_flight_bytes + bytes + need > S->budget) break;
-                    bytes += need;
-                    epoch.push_back(S->pending.front());
-                    S->pending.pop_front();
+            for (int si = 0; si < SLOTS && !S->pending.empty(); ++si) {
+                ebbkc_server::Slot& sl = S->slots[si];
+                if (sl.batch) continue;
+                const bool light_only = si == SLOTS - 1;
+                bool heavy = light_only ? false : S->pending.front().heavy;
+                Start st{&sl, {}, 0};
+                for (auto it = S->pending.begin(); it != S->pending.end() && (int)st.reqs.size() < SLOT_REQUESTS;) {
+                    if (it->heavy != heavy) { ++it; continue; }
+                    const int64_t need = request_bytes(S, it->r);
+                    const bool alone = st.reqs.empty() && busy == 0 && starts.empty();
+                    if (!alone && S->in_flight_bytes + st.bytes + need > S->budget) break;
+                    st.bytes += need;
+                    st.reqs.push_back(it->r);
+                    it = S->pending.erase(it);
                 }
-                S->in_flight += (int64_t)epoch.size();
-                S->in_flight_bytes += bytes;
-                S->max_epoch_requests = std::max<int64_t>(S->max_epoch_requests, (int64_t)epoch.size());
+                if (st.reqs.empty()) continue;
+                S->in_flight += (int64_t)st.reqs.size();
+                S->in_flight_bytes += st.bytes;
+                S->max_epoch_requests = std::max<int64_t>(S->max_epoch_requests, (int64_t)st.reqs.size());
+                starts.push_back(std::move(st));
             }
-            if (epoch.empty() && !progressed) {
+            if (starts.empty() && !progressed) {
                 // nothing to start: wait for a submission, or poll the epochs in flight
                 if (busy == 0) S->cv.wait(lk, [&] { return S->stop || !S->pending.empty(); });
                 else S->cv.wait_for(lk, std::chrono::microseconds(50));
                 continue;
             }
         }
-        if (epoch.empty()) continue;
-        const double t_admit = S->now_ms();
-        std::vector<ebbkc_graph*> gs;
-        std::vector<int32_t> ks;
-        for (auto& r : epoch) {
-            r.admit_ms = t_admit;
-            gs.push_back(S->cat[(size_t)r.graph]);
-            ks.push_back(r.k);
-        }
-        ebbkc_server::Slot& sl = *free_slot;
-        sl.reqs = epoch;
-        sl.bytes = bytes;
-        ebbkc_options o = S->opt;
-        int kmax = 0;
-        for (int k : ks) kmax = std::max(kmax, k);
-        if (kmax <= 2 + 2 * LDS_FRAMES + 4) o.blocks_per_cu = -1;  // share the device with the other slots
-        ebbkc_batch* b = nullptr;
-        ebbkc_status st = batch_create_impl(gs.data(), ks.data(), (int32_t)gs.size(), &o, sl.stream, true, sl.h_tot,
-                                            sl.h_ctr, &b);
-        if (!st) st = enqueue(b, sl.stream);
-        if (!st && hipEventRecord(sl.done, sl.stream) != hipSuccess) st = EBBKC_E_HIP;
-        if (st) {  // the epoch fails as a whole; its requests report the status
-            if (b) {
-                (void)hipStreamSynchronize(sl.stream);
-                batch_destroy_impl(b);
+        for (auto& start : starts) {
+            std::vector<ebbkc_result>& epoch = start.reqs;
+            ebbkc_server::Slot* free_slot = start.slot;
+            const int64_t bytes = start.bytes;
+            const double t_admit = S->now_ms();
+            std::vector<ebbkc_graph*> gs;
+            std::vector<int32_t> ks;
+            for (auto& r : epoch) {
+                r.admit_ms = t_admit;
+                gs.push_back(S->cat[(size_t)r.graph]);
+                ks.push_back(r.k);
             }
-            const double t_done = S->now_ms();
-            std::lock_guard<std::mutex> lk(S->mu);
-            for (auto& r : sl.reqs) {
-                r.status = st;
-                r.count = 0;
-                r.done_ms = t_done;
-                S->done.push_back(r);
+            ebbkc_server::Slot& sl = *free_slot;
+            sl.reqs = epoch;
+            sl.bytes = bytes;
+            ebbkc_options o = S->opt;
+            o.blocks_per_cu = -2;  // leave room on every CU for the epochs of the other slots
+            ebbkc_batch* b = nullptr;
+            ebbkc_status st = batch_create_impl(gs.data(), ks.data(), (int32_t)gs.size(), &o, sl.stream, true, sl.h_tot,
+                                                sl.h_ctr, &b);
+            if (!st) st = enqueue(b, sl.stream);
+            if (!st && hipEventRecord(sl.done, sl.stream) != hipSuccess) st = EBBKC_E_HIP;
+            if (st) {  // the epoch fails as a whole; its requests report the status
+                if (b) {
+                    (void)hipStreamSynchronize(sl.stream);
+                    batch_destroy_impl(b);
+                }
+                const double t_done = S->now_ms();
+                std::lock_guard<std::mutex> lk(S->mu);
+                for (auto& r : sl.reqs) {
+                    r.status = st;
+                    r.count = 0;
+                    r.done_ms = t_done;
+                    S->done.push_back(r);
+                }
+                S->in_flight -= (int64_t)sl.reqs.size();
+                S->in_flight_bytes -= sl.bytes;
+                S->epochs++;
+                sl.reqs.clear();
+                sl.bytes = 0;
+                S->done_cv.notify_all();
+                continue;
             }
-            S->in_flight -= (int64_t)sl.reqs.size();
-            S->in_flight_bytes -= sl.bytes;
-            S->epochs++;
-            sl.reqs.clear();
-            sl.bytes = 0;
-            S->done_cv.notify_all();
-            continue;
+            sl.batch = b;
         }
-        sl.batch = b;
     }
 }
 
@@ -729,10 +760,19 @@ ebbkc_status ebbkc_server_create(ebbkc_graph* const* graphs, int32_t n, const eb
         if (!graphs[i]) { delete S; return EBBKC_E_INVALID_ARG; }
         const int64_t t = graphs[i]->tau + 2;
         S->branch_bytes.push_back((t * t + 7) / 8);
+        std::vector<int64_t> h(257, 0);
         if (graphs[i]->tau >= 1) {
             ebbkc_status st = ebb::arena_impl(graphs[i], nullptr);  // resident before the first request
             if (st) { delete S; return st; }
+            std::vector<int32_t> sc((size_t)graphs[i]->nseeds);
+            if (!sc.empty() &&
+                hipMemcpy(sc.data(), graphs[i]->seed_c, sizeof(int32_t) * sc.size(), hipMemcpyDeviceToHost) != hipSuccess) {
+                delete S;
+                return EBBKC_E_HIP;
+            }
+            for (int32_t c : sc) h[(size_t)std::min(c, 256)]++;
         }
+        S->chist.push_back(std::move(h));
     }
     if (ebb::ensure_tables(graphs[0]->device, nullptr) != hipSuccess) { delete S; return EBBKC_E_HIP; }
     for (auto& sl : S->slots) {
@@ -760,7 +800,7 @@ ebbkc_status ebbkc_server_submit(ebbkc_server* S, int32_t graph, int32_t k, int6
         r.graph = graph;
         r.k = k;
         r.arrival_ms = S->now_ms();
-        S->pending.push_back(r);
+        S->pending.push_back({r, ebb::is_heavy(S, graph, k)});
     }
     S->cv.notify_one();
     if (out_id) *out_id = r.id;

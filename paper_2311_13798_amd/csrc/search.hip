@@ -736,10 +736,13 @@ int64_t grid_blocks(int64_t ntasks, int cus, int blocks_per_cu) {
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, 256, smem) != hipSuccess) return -1;
     if (occ < 1) occ = 1;
     if (blocks_per_cu > 0 && blocks_per_cu < occ) occ = blocks_per_cu;
+    // blocks_per_cu = -2: one persistent workgroup per CU fewer than fit, so a
+    // launch on another stream always finds room
+    if (blocks_per_cu <= -2) occ = occ > 1 ? occ - 1 : 1;
     const int64_t need = (ntasks + 3) / 4;
-    // blocks_per_cu < 0: one workgroup per four tasks, not persistent, so that
+    // blocks_per_cu = -1: one workgroup per four tasks, not persistent, so that
     // launches on other streams get compute units as workgroups retire
-    int64_t grid = blocks_per_cu < 0 ? need : (int64_t)occ * cus;
+    int64_t grid = blocks_per_cu == -1 ? need : (int64_t)occ * cus;
     if (grid > need) grid = need;
     if (grid > 0x7fffffff) grid = 0x7fffffff;
     if (grid < 1) grid = 1;

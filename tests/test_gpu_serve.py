@@ -55,3 +55,39 @@ def test_burst_then_drain(catalogue):
     for i, (g, k) in zip(ids, pairs):
         assert got[i]["count"] == alone[(g, k)]
     S.close()
+
+
+def test_light_requests_run_beside_a_heavy_one():
+    # R-MAT scale 13 at k = 12 takes ~2.3 s alone; requests arriving while it runs start in other
+    # epoch slots and finish long before it, each with its standalone count
+    import time
+
+    import torch
+    import paper_2311_13798_amd as ebb
+    from paper_2311_13798_amd.serve import Server
+    torch.cuda.set_device(0)
+    heavy = ebb.Graph.from_csr(configs.rmat_scale(13))
+    lights = [ebb.Graph.from_csr(g) for g in (configs.er_small(), graphgen.rmat(10, 16, seed=1),
+                                              graphgen.er_planted(300, 0.05, 1, 25, 25, 2))]
+    want_heavy = heavy.count(12)
+    alone = {(i, k): G.count(k) for i, G in enumerate(lights) for k in range(3, 8)}
+    S = Server([heavy] + lights, 1 << 40)
+    hid = S.submit(0, 12)
+    time.sleep(0.05)
+    ids = {}
+    for i in range(45):
+        g, k = i % len(lights), 3 + (i // len(lights)) % 5
+        ids[S.submit(1 + g, k)] = (g, k)
+        time.sleep(0.002)
+    res = {}
+    while len(res) < len(ids) + 1:
+        for r in S.poll(wait=True):
+            res[r["id"]] = r
+    S.close()
+    assert res[hid]["count"] == want_heavy
+    for i, gk in ids.items():
+        assert res[i]["status"] == 0 and res[i]["count"] == alone[gk]
+    before = sum(1 for i in ids if res[i]["done_ms"] < res[hid]["done_ms"])
+    assert before >= 40, before
+    for G in [heavy] + lights:
+        G.close()
