@@ -18,6 +18,8 @@ Also reported on the same JSON line:
                 for the current kernel source exists, else null.
   cpu_baseline  the CPU oracle (degeneracy-ordered vertex branch and bound) timed on the host
                 cores on a bounded sample of the same workload (the full k = 5 count).
+  listing       every 5-clique of the workload (5.5e10 tuples, 1.1 TB) listed rank-range chunk by
+                chunk into one 80 GB device buffer: tuples/s and GB/s written (HBM-write bound).
   batched       many small graphs with per-graph k: one launch per (graph, k) vs the fused
                 batch (one persistent launch per width class, replayed from a HIP graph).
   served        Poisson request streams (50, 200, 1000 requests/s) over a mixed resident catalogue
@@ -63,6 +65,30 @@ def traffic_for(kernel: str, k: int):
         return None
     e = rec.get("launches", {}).get(f"{kernel}@k={k}")
     return None if e is None else e.get("hbm_bytes")
+
+
+def full_listing(ebb, torch, rp, ci, g, k=5, cap=4_000_000_000):
+    """Every k-clique of the workload listed into one reused device buffer of cap tuples (80 GB at
+    k = 5), rank-range chunk by chunk: HBM-write bound, 4 k bytes per tuple."""
+    from paper_2311_13798_amd.listing import list_in_chunks, plan_chunks
+    G = ebb.Graph(rp, ci, g.n)
+    G.count(4)  # sub-branch arena
+    cuts, sizes = plan_chunks(G, k, cap)
+    buf = torch.empty((cap, k), dtype=torch.int32, device="cuda")
+    list_in_chunks(G, k, buf, cap, 0, cuts=cuts[:2])  # warm: first chunk
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    total, hu, nch = list_in_chunks(G, k, buf, cap, 0, cuts=cuts)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t
+    G.close()
+    del buf
+    gbs = total * 4 * k / dt / 1e9
+    log(f"listing k={k}: {total} tuples in {nch} chunks, {dt:.3f}s, {gbs:.1f} GB/s written")
+    return {"k": k, "tuples": total, "chunks": nch, "buffer_tuples": cap, "seconds": round(dt, 4),
+            "tuples_per_s": total / dt, "write_GB_per_s": round(gbs, 2), "bound": "hbm",
+            "write_frac_of_8TBps": round(gbs / 8000.0, 5), "unordered_checksum": str(hu),
+            "order": "unsorted (tuples ascending inside, buffer order by seed rank)"}
 
 
 def systems_forms(ebb, np, torch, configs):
@@ -135,6 +161,7 @@ def main():
     ap.add_argument("--ks", default="5,6,7,8,9", help="comma-separated k values counted in every step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-systems", action="store_true", help="skip the batched and served forms")
+    ap.add_argument("--no-list", action="store_true", help="skip the full k = 5 listing")
     ap.add_argument("--cpu-threads", type=int, default=0)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -216,6 +243,9 @@ def main():
                                for k in ks},
         "roofline": roofline,
     }
+
+    if not args.no_list:
+        line["listing"] = full_listing(ebb, torch, rp, ci, g)
 
     if not args.no_systems:
         line["batched"], line["served"] = systems_forms(ebb, np, torch, configs)

@@ -139,3 +139,23 @@ def test_count_seeds_match_oracle(ebb):
         want = oracle.seed_counts(g, tr["rank"], k, eids)
         assert np.array_equal(out, want), k
     G.close()
+
+
+def test_chunked_listing_equals_the_whole_listing(ebb):
+    import torch
+    from paper_2311_13798_amd.listing import list_in_chunks, plan_chunks
+    g = graphgen.rmat(11, 16, seed=5)
+    G = ebb.Graph.from_csr(g)
+    for k in (4, 5, 6):
+        c, ho, hu, ref = oracle.list_lex(g, k)
+        cap = max(c // 7, 1)
+        cuts, sizes = plan_chunks(G, k, cap)
+        assert sum(sizes) == c and all(0 <= s_ <= cap for s_ in sizes)
+        buf = torch.zeros((cap, k), dtype=torch.int32, device="cuda")
+        parts = []
+        total, ghu, nch = list_in_chunks(G, k, buf, cap, cuts=cuts,
+                                         on_chunk=lambda a, b, w: parts.append(buf[:w].cpu().numpy().copy()))
+        allt = np.concatenate(parts)
+        assert total == c and ghu == hu and nch == len(sizes)
+        assert np.array_equal(allt[np.lexsort(allt.T[::-1])], ref)
+    G.close()
