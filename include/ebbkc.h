@@ -119,6 +119,17 @@ ebbkc_status ebbkc_prepare(const int32_t *row_ptr, const int32_t *col_idx, int32
  * edge-oriented branch and bound. */
 ebbkc_status ebbkc_count(ebbkc_graph *g, int32_t k, uint64_t *out_count, void *stream);
 
+/* The same count exactly in 128 bits: out_count[0] low word, out_count[1]
+ * high word (near the maximum clique size counts pass 2^64: C(70, 35) > 2^64;
+ * Section 6.2 (2) counts k up to omega).  E_OVERFLOW only past 2^128. */
+ebbkc_status ebbkc_count128(ebbkc_graph *g, int32_t k, uint64_t out_count[2], void *stream);
+
+/* Size omega of a maximum clique: the largest k with N_k > 0, by binary search
+ * over k <= tau + 2 (Section 4.2: a seed's sub-branch has at most tau
+ * vertices, so no clique exceeds tau + 2).  0 for an empty graph, 1 without
+ * edges. */
+ebbkc_status ebbkc_max_clique_size(ebbkc_graph *g, int32_t *out, void *stream);
+
 /* Number of k-cliques whose seed edge (the edge of the clique that comes
  * first in pi_tau) has rank in [r_begin, r_end).  Summed over a partition of
  * [0, m) this is the full count (every k-clique is listed exactly once,

@@ -47,7 +47,8 @@ class ebbkc_info(ctypes.Structure):
                 ("max_degree", ctypes.c_int32), ("device_bytes", ctypes.c_int64), ("prepare_ms", ctypes.c_double)]
 
 
-EXPORTED = ("ebbkc_default_options", "ebbkc_prepare", "ebbkc_count", "ebbkc_count_range", "ebbkc_count_seeds",
+EXPORTED = ("ebbkc_default_options", "ebbkc_prepare", "ebbkc_count", "ebbkc_count128", "ebbkc_max_clique_size",
+            "ebbkc_count_range", "ebbkc_count_seeds",
             "ebbkc_list", "ebbkc_export", "ebbkc_info_get", "ebbkc_last_timing", "ebbkc_last_work",
             "ebbkc_last_work_class", "ebbkc_destroy", "ebbkc_strerror", "ebbkc_batch_create", "ebbkc_batch_run", "ebbkc_batch_tune", "ebbkc_batch_info",
             "ebbkc_batch_destroy", "ebbkc_server_create", "ebbkc_server_submit", "ebbkc_server_poll",
@@ -71,6 +72,8 @@ def load_library(path: str = LIB_PATH):
     lib.ebbkc_prepare.argtypes = [vp, vp, i32, i64, i32, ctypes.POINTER(ebbkc_options), vp, ctypes.POINTER(vp)]
     lib.ebbkc_count.argtypes = [vp, i32, pu64, vp]
     lib.ebbkc_count_range.argtypes = [vp, i32, i64, i64, pu64, vp]
+    lib.ebbkc_count128.argtypes = [vp, i32, pu64, vp]
+    lib.ebbkc_max_clique_size.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), vp]
     lib.ebbkc_count_seeds.argtypes = [vp, i32, vp, i64, i32, vp, vp]
     lib.ebbkc_list.argtypes = [vp, i32, i64, i64, vp, u64, u32, pu64, vp, vp]
     lib.ebbkc_export.argtypes = [vp, i32, vp, i32, vp]
@@ -98,7 +101,7 @@ def load_library(path: str = LIB_PATH):
         getattr(lib, f).restype = ctypes.c_int
     lib.ebbkc_strerror.argtypes = [i32]
     lib.ebbkc_strerror.restype = ctypes.c_char_p
-    for f in ("ebbkc_prepare", "ebbkc_count", "ebbkc_count_range", "ebbkc_count_seeds", "ebbkc_list",
+    for f in ("ebbkc_prepare", "ebbkc_count", "ebbkc_count_range", "ebbkc_count128", "ebbkc_max_clique_size", "ebbkc_count_seeds", "ebbkc_list",
               "ebbkc_export", "ebbkc_info_get", "ebbkc_last_timing", "ebbkc_last_work", "ebbkc_last_work_class"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
@@ -155,6 +158,18 @@ def ebbkc_prepare(row_ptr, col_idx, n: int, nnz: int, options: ebbkc_options | N
 def ebbkc_count(h, k: int, stream=None) -> int:
     out = ctypes.c_uint64()
     _check(load_library().ebbkc_count(h, k, ctypes.byref(out), _stream(stream)), "ebbkc_count")
+    return int(out.value)
+
+
+def ebbkc_count128(h, k: int, stream=None) -> int:
+    out = (ctypes.c_uint64 * 2)()
+    _check(load_library().ebbkc_count128(h, k, out, _stream(stream)), "ebbkc_count128")
+    return int(out[0]) | (int(out[1]) << 64)
+
+
+def ebbkc_max_clique_size(h, stream=None) -> int:
+    out = ctypes.c_int32()
+    _check(load_library().ebbkc_max_clique_size(h, ctypes.byref(out), _stream(stream)), "ebbkc_max_clique_size")
     return int(out.value)
 
 
@@ -359,6 +374,12 @@ class Graph:
 
     def count(self, k: int) -> int:
         return ebbkc_count(self._h, k)
+
+    def count128(self, k: int) -> int:
+        return ebbkc_count128(self._h, k)
+
+    def max_clique_size(self) -> int:
+        return ebbkc_max_clique_size(self._h)
 
     def count_range(self, k: int, r_begin: int, r_end: int) -> int:
         return ebbkc_count_range(self._h, k, r_begin, r_end)

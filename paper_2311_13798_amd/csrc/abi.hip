@@ -79,6 +79,42 @@ ebbkc_status ebbkc_count(ebbkc_graph* g, int32_t k, uint64_t* out_count, void* s
     return ebb::count_impl(g, k, 0, g->m, nullptr, 0, nullptr, out_count, (hipStream_t)stream);
 }
 
+ebbkc_status ebbkc_count128(ebbkc_graph* g, int32_t k, uint64_t out_count[2], void* stream) {
+    if (!g || !out_count) return EBBKC_E_INVALID_ARG;
+    uint64_t lo = 0;
+    ebbkc_status st = ebbkc_count(g, k, &lo, stream);
+    if (st == EBBKC_OK) {
+        out_count[0] = lo;
+        out_count[1] = 0;
+        return EBBKC_OK;
+    }
+    if (st != EBBKC_E_OVERFLOW || g->last_total_ovf) return st;
+    out_count[0] = g->last_total[0];
+    out_count[1] = g->last_total[1];
+    return EBBKC_OK;
+}
+
+ebbkc_status ebbkc_max_clique_size(ebbkc_graph* g, int32_t* out, void* stream) {
+    if (!g || !out) return EBBKC_E_INVALID_ARG;
+    if (g->n == 0) { *out = 0; return EBBKC_OK; }
+    if (g->m == 0) { *out = 1; return EBBKC_OK; }
+    // N_k > 0 is monotone in k (a k-clique holds (k-1)-cliques); N_2 = m > 0 and
+    // N_k = 0 past tau + 2 (every k-clique lies in the sub-branch of its seed,
+    // which has at most tau vertices)
+    int lo = 2, hi = g->tau + 2;
+    while (lo < hi) {
+        const int mid = lo + (hi - lo + 1) / 2;
+        uint64_t c[2] = {0, 0};
+        ebbkc_status st = ebbkc_count128(g, mid, c, stream);
+        const bool some = st == EBBKC_OK ? (c[0] | c[1]) != 0 : st == EBBKC_E_OVERFLOW;
+        if (st != EBBKC_OK && st != EBBKC_E_OVERFLOW) return st;
+        if (some) lo = mid;
+        else hi = mid - 1;
+    }
+    *out = lo;
+    return EBBKC_OK;
+}
+
 ebbkc_status ebbkc_count_range(ebbkc_graph* g, int32_t k, int64_t r_begin, int64_t r_end, uint64_t* out_count,
                                void* stream) {
     if (!g || !out_count) return EBBKC_E_INVALID_ARG;

@@ -328,6 +328,10 @@ static ebbkc_status read_total(ebbkc_graph* g, uint64_t* out, hipStream_t s) {
     const int err = (int)g->h_counters[6];
     if (err & ERR_WIDTH) return EBBKC_E_WIDTH;
     if (err & ERR_DEPTH) return EBBKC_E_K_RANGE;
+    // the exact total is 128 bits wide; the 64-bit result is an error past 2^64
+    g->last_total[0] = g->h_counters[4];
+    g->last_total[1] = g->h_counters[5];
+    g->last_total_ovf = (err & ERR_OVERFLOW) != 0;
     if ((err & ERR_OVERFLOW) || g->h_counters[5] != 0) return EBBKC_E_OVERFLOW;
     *out = g->h_counters[4];
     for (int i = 0; i < 4; ++i) g->last_work[i] = 0;

@@ -62,6 +62,8 @@ struct ebbkc_graph {
     double last_ms[4] = {0, 0, 0, 0};
     uint64_t last_work[4] = {0, 0, 0, 0};
     uint64_t last_work_class[4][4] = {};
+    uint64_t last_total[2] = {0, 0};  // the last count, 128 bits
+    bool last_total_ovf = false;      // it reached 2^128
     int64_t device_bytes = 0;
 };
 

@@ -57,39 +57,60 @@ __device__ uint64_t binom(int n, int r) {
     return (uint64_t)c;
 }
 
-__device__ __forceinline__ uint64_t mul_sat(uint64_t a, uint64_t b) {
-    if (a == 0 || b == 0) return 0;
-    if (a == UINT64_MAX || b == UINT64_MAX) return UINT64_MAX;
-    return __umul64hi(a, b) ? UINT64_MAX : a * b;
+typedef unsigned __int128 u128;
+constexpr u128 U128_MAX = ~(u128)0;
+
+// C(n, r) exactly in 128 bits; sets ovf when it does not fit
+__device__ u128 binom128(int n, int r, bool& ovf) {
+    if (r < 0 || r > n) return 0;
+    if (r > n - r) r = n - r;
+    const uint64_t b = binom(n, r);
+    if (b != UINT64_MAX) return b;
+    // C(n-r+j, j) = C(n-r+j-1, j-1) (n-r+j) / j, exact: with c = q j + s,
+    // c m / j = q m + s m / j
+    u128 c = 1;
+    for (int j = 1; j <= r; ++j) {
+        const uint64_t m = (uint64_t)(n - r + j);
+        const u128 q = c / (uint64_t)j, sm = (c % (uint64_t)j) * m;
+        if (q > U128_MAX / m) { ovf = true; return 0; }
+        c = q * m + sm / (uint64_t)j;
+    }
+    return c;
 }
-__device__ __forceinline__ uint64_t add_sat(uint64_t a, uint64_t b) {
-    const uint64_t c = a + b;
-    return (c < a || a == UINT64_MAX || b == UINT64_MAX) ? UINT64_MAX : c;
+
+__device__ __forceinline__ u128 mul128(u128 a, u128 b, bool& ovf) {
+    if (a == 0 || b == 0) return 0;
+    if (a > U128_MAX / b) { ovf = true; return 0; }
+    return a * b;
 }
 
 // l-cliques of a 2-plex with f vertices adjacent to all others and p
-// non-adjacent pairs: sum_j C(p,j) 2^j C(f, l-j)
-__device__ uint64_t twoplex_count(int f, int p, int l) {
-    uint64_t s = 0;
+// non-adjacent pairs: sum_j C(p,j) 2^j C(f, l-j), exactly in 128 bits
+__device__ u128 twoplex_count(int f, int p, int l, bool& ovf) {
+    u128 s = 0;
     const int jmax = p < l ? p : l;
     for (int j = 0; j <= jmax; ++j) {
         if (l - j > f) continue;
-        uint64_t t = mul_sat(binom(p, j), binom(f, l - j));
-        t = (j >= 64) ? (t ? UINT64_MAX : 0) : mul_sat(t, 1ull << j);
-        s = add_sat(s, t);
+        u128 t = mul128(binom128(p, j, ovf), binom128(f, l - j, ovf), ovf);
+        if (t == 0) continue;
+        if (j >= 128 || (t >> (127 - j)) != 0) { ovf = true; return 0; }
+        t <<= j;
+        s += t;
+        if (s < t) { ovf = true; return 0; }
     }
     return s;
 }
 
-// 128-bit accumulator; a saturated (UINT64_MAX) term marks overflow
+// exact 128-bit accumulator with an overflow flag
 struct Acc {
-    uint64_t lo, hi;
-    __device__ void add(uint64_t v) {
-        const uint64_t o = lo;
-        lo += v;
-        if (lo < o) ++hi;
-        if (v == UINT64_MAX) hi |= 1ull << 62;
+    u128 v;
+    bool ovf;
+    __device__ void add(u128 x) {
+        v += x;
+        ovf |= v < x;
     }
+    __device__ uint64_t lo() const { return (uint64_t)v; }
+    __device__ uint64_t hi() const { return (uint64_t)(v >> 64); }
 };
 
 template <int W>
@@ -207,7 +228,7 @@ __global__ __launch_bounds__(256, (W <= 3 ? 3 : 2)) void k_search(SearchArgs a) 
     const int opts = a.opts;
     const bool rule1 = opts & OPT_RULE1, rule2 = opts & OPT_RULE2, et = opts & OPT_ET, t2 = opts & OPT_TPLEX2;
     const bool work = opts & OPT_WORK;
-    Acc acc{0, 0};
+    Acc acc{0, false};
     uint64_t wk_tasks = 0, wk_nodes = 0, wk_ops = 0;
 
     for (;;) {
@@ -224,7 +245,7 @@ __global__ __launch_bounds__(256, (W <= 3 ? 3 : 2)) void k_search(SearchArgs a) 
         const int c = uniform_i32(A.seed_c[slot]);
         const int64_t ro = A.row_off[slot], vo = A.vtx_off[slot];
         wk_tasks += work;
-        Acc tacc{0, 0};
+        Acc tacc{0, false};
         if (k == 3) {  // l = 1 at the root: |V(g_i)| triangles through the seed edge
             tacc.add((uint64_t)c);
             goto task_done;
@@ -254,7 +275,7 @@ __global__ __launch_bounds__(256, (W <= 3 ? 3 : 2)) void k_search(SearchArgs a) 
 
         // Count a node that needs no branching: returns true and sets val, or
         // false when the node (l >= 4) must be branched on.
-        auto finish = [&](const uint64_t (&P)[W], int l, uint64_t& val) -> bool {
+        auto finish = [&](const uint64_t (&P)[W], int l, u128& val) -> bool {
             const int pc = popcW(P);
             val = 0;
             if (work) { wk_nodes += 1; wk_ops += W; }
@@ -280,10 +301,10 @@ __global__ __launch_bounds__(256, (W <= 3 ? 3 : 2)) void k_search(SearchArgs a) 
             if (l == 2) { val = twoE / 2; return true; }
             if (et) {
                 const int mind = wmin_i32(mn);
-                if (mind >= pc - 1) { val = binom(pc, l); return true; }
+                if (mind >= pc - 1) { val = binom128(pc, l, tacc.ovf); return true; }
                 if (t2 && mind >= pc - 2) {
                     const int nfull = (int)wsum_u32((uint32_t)nf);
-                    val = twoplex_count(nfull, (pc - nfull) / 2, l);
+                    val = twoplex_count(nfull, (pc - nfull) / 2, l, tacc.ovf);
                     return true;
                 }
             }
@@ -587,9 +608,31 @@ __global__ __launch_bounds__(256, (W <= 3 ? 3 : 2)) void k_search(SearchArgs a) 
         const bool whole = x0 == 0 && x1 >= c;
         bool active = true;
         if (whole) {
-            uint64_t rootval = 0;
+            u128 rootval = 0;
             active = !finish(P0, l0, rootval);
             if (!active) tacc.add(rootval);
+        } else if (et && l0 >= 3) {
+            // a root split over several tasks that is a clique: this task's
+            // part is the l0-cliques whose first vertex x lies in [x0, x1),
+            // sum_x C(c-1-x, l0-1)
+            int mn = 1 << 30;
+#pragma unroll
+            for (int q = 0; q < W; ++q) {
+                const int v = lane + 64 * q;
+                if (v < c) {
+                    int d = 0;
+#pragma unroll
+                    for (int w = 0; w < W; ++w) d += popc64(P0[w] & M.rows[v][w]);
+                    mn = d < mn ? d : mn;
+                }
+            }
+            if (wmin_i32(mn) >= c - 1) {
+                u128 part = 0;
+                const int xe = x1 < c ? x1 : c;
+                for (int x = x0; x < xe; ++x) part += binom128(c - 1 - x, l0 - 1, tacc.ovf);
+                tacc.add(part);
+                active = false;
+            }
         }
         if (active && (l0 == 4 || l0 == 5)) {
             children_by_lanes(P0, l0, x0, x1);
@@ -671,7 +714,7 @@ __global__ __launch_bounds__(256, (W <= 3 ? 3 : 2)) void k_search(SearchArgs a) 
                 }
                 if (dc < lc) continue;
             }
-            uint64_t v = 0;
+            u128 v = 0;
             if (finish(Pc, lc, v)) { tacc.add(v); continue; }
             if (lc == 4 || lc == 5) { children_by_lanes(Pc, lc, 0, c); continue; }
             if (sp >= LDS_FRAMES + (gfr ? GLOBAL_FRAMES : 0)) {
@@ -696,19 +739,16 @@ __global__ __launch_bounds__(256, (W <= 3 ? 3 : 2)) void k_search(SearchArgs a) 
 
         }
     task_done:
-        if (tacc.hi && lane == 0) atomicOr(a.err, ERR_OVERFLOW);
-        if (a.per_task && lane == 0) a.per_task[it] = tacc.lo;
+        if (tacc.ovf && lane == 0) atomicOr(a.err, ERR_OVERFLOW);
+        if (a.per_task && lane == 0) a.per_task[it] = tacc.lo();
         if (a.graph_total) {
-            if (lane == 0 && tacc.lo) {
-                const unsigned long long old = atomicAdd(&a.graph_total[2 * gi], (unsigned long long)tacc.lo);
-                if (old + tacc.lo < old) atomicAdd(&a.graph_total[2 * gi + 1], 1ull);
+            if (lane == 0 && tacc.lo()) {
+                const unsigned long long old = atomicAdd(&a.graph_total[2 * gi], (unsigned long long)tacc.lo());
+                if (old + tacc.lo() < old) atomicAdd(&a.graph_total[2 * gi + 1], 1ull);
             }
-            if (lane == 0 && tacc.hi) atomicAdd(&a.graph_total[2 * gi + 1], (unsigned long long)tacc.hi);
+            if (lane == 0 && tacc.hi()) atomicAdd(&a.graph_total[2 * gi + 1], (unsigned long long)tacc.hi());
         } else {
-            const uint64_t o = acc.lo;
-            acc.lo += tacc.lo;
-            if (acc.lo < o) ++acc.hi;
-            acc.hi += tacc.hi;
+            acc.add(tacc.v);
         }
         wave_sync();
     }
@@ -717,10 +757,11 @@ __global__ __launch_bounds__(256, (W <= 3 ? 3 : 2)) void k_search(SearchArgs a) 
         atomicAdd(&a.work[1], (unsigned long long)wk_nodes);
         atomicAdd(&a.work[2], (unsigned long long)wk_ops);
     }
-    if (lane == 0 && (acc.lo || acc.hi)) {
-        const unsigned long long old = atomicAdd(&a.total[0], (unsigned long long)acc.lo);
-        const unsigned long long carry = (old + acc.lo < old) ? 1ull : 0ull;
-        if (acc.hi + carry) atomicAdd(&a.total[1], (unsigned long long)(acc.hi + carry));
+    if (acc.ovf && lane == 0) atomicOr(a.err, ERR_OVERFLOW);
+    if (lane == 0 && acc.v) {
+        const unsigned long long old = atomicAdd(&a.total[0], (unsigned long long)acc.lo());
+        const unsigned long long carry = (old + acc.lo() < old) ? 1ull : 0ull;
+        if (acc.hi() + carry) atomicAdd(&a.total[1], (unsigned long long)(acc.hi() + carry));
     }
 }
 

@@ -12,7 +12,7 @@ HEADER = os.path.join(ROOT, "include", "ebbkc.h")
 def declared_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(ebbkc_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(ebbkc_[a-z0-9_]+)\s*\(", text)))
 
 
 def test_header_declares_the_boundary():
