@@ -74,6 +74,15 @@ def main():
         ks = [1, 2, 3, 4, 5, 6] + ([7] if args.with_k7 else [])
         rec = graph_record(g, ks=ks, sample_ks=((5, 1000), (7, 100), (9, 70)), nsample=300, seed=1)
         json.dump(rec, open(os.path.join(OUT, "rmat18.json"), "w"), indent=1)
+    if args.only in ("", "rmat18_list5"):
+        # the full k = 5 listing of R-MAT s18 (5.5e10 tuples): count and order-independent checksum
+        g = configs.rmat18()
+        t = time.time()
+        c, ho, hu, _ = oracle.list_lex(g, 5, want_tuples=False)
+        rec = {"name": g.name, "sha256": g.sha256(), "k": 5, "count": c, "unordered": str(hu),
+               "ordered": str(ho), "oracle_seconds": round(time.time() - t, 1)}
+        print("rmat18 list k=5", c, hu, f"{time.time() - t:.1f}s", flush=True)
+        json.dump(rec, open(os.path.join(OUT, "rmat18_list5.json"), "w"), indent=1)
     if args.only in ("", "cl1m"):
         # Chung-Lu n = 10^6 with 200 planted cliques (the dense-branch early-termination workload)
         g = configs.cl_planted()

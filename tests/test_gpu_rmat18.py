@@ -57,3 +57,20 @@ def test_sampled_seed_counts(setup, k):
     out = np.zeros(len(eids), np.uint64)
     ebb.ebbkc_count_seeds(G.handle, k, eids, out)
     assert [int(x) for x in out] == [int(x) for x in rec["counts"]]
+
+
+def test_full_k5_listing_in_chunks(setup):
+    # all 5.5e10 5-cliques (1.1 TB) listed rank-range chunk by chunk into one 80 GB buffer; the count
+    # and the order-independent checksum of the whole listing against the oracle's
+    import torch
+    from paper_2311_13798_amd.listing import list_in_chunks
+    ebb, fx, g, G = setup
+    ref = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "rmat18_list5.json")))
+    assert ref["sha256"] == fx["sha256"]
+    cap = 4_000_000_000
+    buf = torch.empty((cap, 5), dtype=torch.int32, device="cuda")
+    total, hu, nch = list_in_chunks(G, 5, buf, cap)
+    del buf
+    assert total == ref["count"] == fx["counts"]["5"]
+    assert str(hu) == ref["unordered"]
+    assert nch > 1
