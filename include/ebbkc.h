@@ -66,7 +66,11 @@ enum { EBBKC_PTR_HOST = 0, EBBKC_PTR_DEVICE = 1 };
  * no switch changes any count or listing. */
 typedef struct {
     int32_t early_termination; /* 1 (default): clique / 2-plex closed forms (Section 5) */
-    int32_t t_plex;            /* largest t handled in closed form: 1 = clique only, 2 (default) */
+    int32_t t_plex;            /* largest t whose t-plexes (every vertex misses at most t-1
+                                  others) are counted in closed form: 1 cliques, 2 also 2-plexes
+                                  (Algorithm kC2Plex), 3 also 3-plexes (Algorithm kCtPlex, whose
+                                  missing pairs form paths and cycles); 0 (default) the rule of
+                                  Section 6.1: 2 when k <= tau/2, else 3 */
     int32_t rule1;             /* 1 (default): colour pruning Rule (1), Section 4.3 */
     int32_t rule2;             /* 1 (default): colour pruning Rule (2), Section 4.3 */
     int32_t waves_per_block;   /* workgroup size in wavefronts (default 4) */

@@ -11,7 +11,7 @@ void ebbkc_default_options(ebbkc_options* opt) {
     if (!opt) return;
     *opt = ebbkc_options{};
     opt->early_termination = 1;
-    opt->t_plex = 2;
+    opt->t_plex = 0;
     opt->rule1 = 1;
     opt->rule2 = 1;
     opt->waves_per_block = 4;

@@ -8,7 +8,7 @@
 namespace ebb {
 
 enum : int { ERR_WIDTH = 1, ERR_OVERFLOW = 2, ERR_DEPTH = 4, ERR_CAP = 8 };
-enum : int { OPT_ET = 1, OPT_TPLEX2 = 2, OPT_RULE1 = 4, OPT_RULE2 = 8, OPT_WORK = 16 };
+enum : int { OPT_ET = 1, OPT_RULE1 = 4, OPT_RULE2 = 8, OPT_WORK = 16 };
 
 constexpr int MAX_W = 4;              // widest bitmap class: 256 vertices
 constexpr int LDS_FRAMES = 12;        // search frames kept in LDS (nodes with l >= 6)
@@ -104,6 +104,8 @@ struct SearchArgs {
     int32_t k;
     int32_t opts;
     float k4_weight;            // dense 4-clique evaluation cost weight (<= 0: never)
+    int32_t tplex;              // largest t counted in closed form (1..3), 0: 2 when 2k <= tau, else 3
+    int32_t tau;                // the graph's tau (for tplex = 0)
     unsigned long long* next;
     unsigned long long* total;  // [lo, hi]
     unsigned long long* work;   // [tasks, nodes, word ops]
@@ -121,6 +123,7 @@ struct SearchArgs {
     const ArenaView* views;
     const int32_t* task_graph;
     const int32_t* graph_k;
+    const int32_t* graph_tau;
     unsigned long long* graph_total;
 };
 

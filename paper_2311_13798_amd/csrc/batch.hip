@@ -38,6 +38,7 @@ struct ebbkc_batch {
     // device
     ebb::ArenaView* views = nullptr;
     int32_t* gk = nullptr;
+    int32_t* gtau = nullptr;
     int64_t* tasks = nullptr;
     int32_t* tgraph = nullptr;
     unsigned long long* gtot = nullptr;  // 2 per graph
@@ -136,7 +137,6 @@ __global__ void k_bclear(unsigned long long* __restrict__ a, int64_t na, unsigne
 int opts_of(const ebbkc_options& o) {
     int f = 0;
     if (o.early_termination) f |= OPT_ET;
-    if (o.t_plex >= 2) f |= OPT_TPLEX2;
     if (o.rule1) f |= OPT_RULE1;
     if (o.rule2) f |= OPT_RULE2;
     return f;
@@ -268,6 +268,8 @@ ebbkc_status enqueue(ebbkc_batch* b, hipStream_t s) {
         a.graph_total = b->gtot;
         a.opts = opts_of(b->opt);
         a.k4_weight = k4_weight_of(b->opt.dense_k4);
+        a.tplex = b->opt.t_plex;
+        a.graph_tau = b->gtau;
         a.next = b->ctr + (W - 1);
         a.total = b->ctr + 4;
         a.work = b->ctr + 8;
@@ -371,7 +373,7 @@ void batch_destroy_impl(ebbkc_batch* b) {
     free_tasks(b);
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
-    void* ptrs[] = {b->views, b->gk, b->gtot, b->ctr};
+    void* ptrs[] = {b->views, b->gk, b->gtau, b->gtot, b->ctr};
     for (void* p : ptrs) dev_free(b, p, b->mem_stream);
     if (b->own_host) {
         if (b->h_tot) (void)hipHostFree(b->h_tot);
@@ -418,6 +420,7 @@ ebbkc_status batch_create_impl(ebbkc_graph* const* graphs, const int32_t* ks, in
     auto fail = [&](ebbkc_status st) { batch_destroy_impl(b); return st; };
     if (dev_alloc(b, (void**)&b->views, sizeof(ArenaView) * n, s) != hipSuccess) return fail(EBBKC_E_OOM);
     if (dev_alloc(b, (void**)&b->gk, sizeof(int32_t) * n, s) != hipSuccess) return fail(EBBKC_E_OOM);
+    if (dev_alloc(b, (void**)&b->gtau, sizeof(int32_t) * n, s) != hipSuccess) return fail(EBBKC_E_OOM);
     if (dev_alloc(b, (void**)&b->gtot, sizeof(unsigned long long) * 2 * n, s) != hipSuccess) return fail(EBBKC_E_OOM);
     if (dev_alloc(b, (void**)&b->ctr, sizeof(unsigned long long) * 16, s) != hipSuccess) return fail(EBBKC_E_OOM);
     if (h_tot && h_ctr) {
@@ -430,8 +433,11 @@ ebbkc_status batch_create_impl(ebbkc_graph* const* graphs, const int32_t* ks, in
         if (hipHostMalloc((void**)&b->h_ctr, sizeof(unsigned long long) * 16, hipHostMallocDefault) != hipSuccess)
             return fail(EBBKC_E_OOM);
     }
+    std::vector<int32_t> taus((size_t)n);
+    for (int i = 0; i < n; ++i) taus[(size_t)i] = graphs[i]->tau;
     if (hipMemcpyAsync(b->views, views.data(), sizeof(ArenaView) * n, hipMemcpyHostToDevice, s) != hipSuccess ||
-        hipMemcpyAsync(b->gk, b->ks.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s) != hipSuccess)
+        hipMemcpyAsync(b->gk, b->ks.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(b->gtau, taus.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s) != hipSuccess)
         return fail(EBBKC_E_HIP);
     if (ensure_tables(b->device, s) != hipSuccess) return fail(EBBKC_E_HIP);
     if (!async_mem) {

@@ -39,7 +39,6 @@ hipError_t ensure_binom(int dev, hipStream_t s) {
 int opts_of(const ebbkc_options& o) {
     int f = 0;
     if (o.early_termination) f |= OPT_ET;
-    if (o.t_plex >= 2) f |= OPT_TPLEX2;
     if (o.rule1) f |= OPT_RULE1;
     if (o.rule2) f |= OPT_RULE2;
     if (o.count_work) f |= OPT_WORK;
@@ -409,6 +408,8 @@ static ebbkc_status run_tasks(ebbkc_graph* g, int32_t k, const int64_t* tsorted,
         a.k = k;
         a.opts = opts_of(g->opt);
         a.k4_weight = k4_weight_of(g->opt.dense_k4);
+        a.tplex = g->opt.t_plex;
+        a.tau = g->tau;
         a.next = (unsigned long long*)(g->d_counters + W - 1);
         a.total = (unsigned long long*)(g->d_counters + 4);
         a.work = (unsigned long long*)(g->d_counters + 16 + 4 * (W - 1));

@@ -60,28 +60,56 @@ __device__ uint64_t binom(int n, int r) {
 typedef unsigned __int128 u128;
 constexpr u128 U128_MAX = ~(u128)0;
 
-// C(n, r) exactly in 128 bits; sets ovf when it does not fit
-__device__ u128 binom128(int n, int r, bool& ovf) {
-    if (r < 0 || r > n) return 0;
-    if (r > n - r) r = n - r;
-    const uint64_t b = binom(n, r);
-    if (b != UINT64_MAX) return b;
-    // C(n-r+j, j) = C(n-r+j-1, j-1) (n-r+j) / j, exact: with c = q j + s,
-    // c m / j = q m + s m / j
-    u128 c = 1;
-    for (int j = 1; j <= r; ++j) {
-        const uint64_t m = (uint64_t)(n - r + j);
-        const u128 q = c / (uint64_t)j, sm = (c % (uint64_t)j) * m;
-        if (q > U128_MAX / m) { ovf = true; return 0; }
-        c = q * m + sm / (uint64_t)j;
+// C(n, r) for n <= 257, r <= 128 in 128 bits (Pascal's rule, built once per
+// device); both words all ones when it does not fit
+constexpr int B128_N = 258, B128_R = 129;
+__device__ uint64_t g_binom128[B128_N * B128_R * 2];
+
+__global__ void k_binom128_init() {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    for (int n = 0; n < B128_N; ++n) {
+        for (int r = 0; r < B128_R; ++r) {
+            u128 v;
+            bool sat = false;
+            if (r == 0) v = 1;
+            else if (r > n) v = 0;
+            else {
+                const uint64_t* a = &g_binom128[((n - 1) * B128_R + r - 1) * 2];
+                const uint64_t* b = &g_binom128[((n - 1) * B128_R + r) * 2];
+                const bool sa = a[0] == ~0ull && a[1] == ~0ull, sb = b[0] == ~0ull && b[1] == ~0ull;
+                const u128 x = ((u128)a[1] << 64) | a[0], y = ((u128)b[1] << 64) | b[0];
+                v = x + y;
+                sat = sa || sb || v < x;
+            }
+            uint64_t* o = &g_binom128[(n * B128_R + r) * 2];
+            o[0] = sat ? ~0ull : (uint64_t)v;
+            o[1] = sat ? ~0ull : (uint64_t)(v >> 64);
+        }
     }
-    return c;
 }
 
+// C(n, r) exactly in 128 bits; sets ovf when it does not fit
+__device__ __forceinline__ u128 binom128(int n, int r, bool& ovf) {
+    if (r < 0 || r > n) return 0;
+    if (r > n - r) r = n - r;
+    if (r == 0) return 1;
+    if (n >= B128_N) { ovf = true; return 0; }
+    const uint64_t* e = &g_binom128[(n * B128_R + r) * 2];
+    const uint64_t lo = e[0], hi = e[1];
+    if (lo == ~0ull && hi == ~0ull) { ovf = true; return 0; }
+    return ((u128)hi << 64) | lo;
+}
+
+// a * b in 128 bits; sets ovf when it does not fit
 __device__ __forceinline__ u128 mul128(u128 a, u128 b, bool& ovf) {
-    if (a == 0 || b == 0) return 0;
-    if (a > U128_MAX / b) { ovf = true; return 0; }
-    return a * b;
+    const uint64_t ah = (uint64_t)(a >> 64), al = (uint64_t)a, bh = (uint64_t)(b >> 64), bl = (uint64_t)b;
+    if (ah && bh) { ovf = true; return 0; }
+    const u128 low = (u128)al * bl;
+    const u128 mid = (u128)ah * bl + (u128)al * bh;  // one of the two terms is zero
+    if (mid >> 64) { ovf = true; return 0; }
+    const u128 r = low + (mid << 64);
+    if (r < low) { ovf = true; return 0; }
+    return r;
 }
 
 // l-cliques of a 2-plex with f vertices adjacent to all others and p
@@ -212,6 +240,171 @@ __device__ __forceinline__ uint64_t lane_triangles(const SearchMem<W>& M, const 
     return dense ? C3 - Mp * (q64 - 2) + s2 - t : (uint64_t)t;
 }
 
+// l-cliques of a 3-plex P (every vertex misses at most two others of P):
+// the coefficient of x^l in the independence polynomial of the missing
+// pairs H[P], a disjoint union of paths and cycles; Algorithm kCtPlex
+// reaches the same sets by branching on H.  Lanes walk the components from
+// their vertices into length histograms; the product of path polynomials
+// (sum_i C(L-i+1, i) x^i) and cycle polynomials (sum_i [C(L-i, i) +
+// C(L-i-1, i-1)] x^i) is formed in LDS, lane j mod 64 owning coefficient j.
+// Needs l < pc (so l < 256); sets ovf when the coefficient reaches 2^128.
+template <int W>
+__device__ __forceinline__ u128 threeplex_count(SearchMem<W>& M, const uint64_t (&P)[W], int pc, int l, bool& ovf) {
+const int lane = lane_id();
+        int32_t* hp = M.pq[0];   // paths by length
+        int32_t* hcy = M.pq[1];  // cycles by length
+        for (int i = lane; i < 257; i += 64) { hp[i] = 0; hcy[i] = 0; }
+        {
+            int base = 0;
+#pragma unroll
+            for (int q = 0; q < W; ++q) {
+                if ((P[q] >> lane) & 1) M.vl[base + popc64(P[q] & lanemask_lt())] = (int16_t)(lane + 64 * q);
+                base += popc64(P[q]);
+            }
+        }
+        wave_sync();
+        const int rounds = (pc + 63) >> 6;
+        for (int t = 0; t < rounds; ++t) {
+            const int j = 64 * t + lane;
+            if (j < pc) {
+                const int v = M.vl[j];
+                int mv = -1;  // P & ~row(v) holds v itself
+#pragma unroll
+                for (int w = 0; w < W; ++w) mv += popc64(P[w] & ~M.rows[v][w]);
+                M.md[v] = (int16_t)mv;
+            }
+        }
+        wave_sync();
+        // an H-neighbour of cur other than avoid (-1: none)
+        auto hnext = [&](int cur, int avoid) -> int {
+            int r = -1;
+#pragma unroll
+            for (int w = W - 1; w >= 0; --w) {
+                uint64_t h = P[w] & ~M.rows[cur][w];
+                if (w == (cur >> 6)) h &= ~(1ull << (cur & 63));
+                if (avoid >= 0 && w == (avoid >> 6)) h &= ~(1ull << (avoid & 63));
+                if (h) r = w * 64 + __builtin_ctzll(h);
+            }
+            return r;
+        };
+        for (int t = 0; t < rounds; ++t) {
+            const int j = 64 * t + lane;
+            if (j >= pc) continue;
+            const int v = M.vl[j];
+            const int mv = M.md[v];
+            if (mv <= 1) {  // end of a path (or a lone vertex): walk to the other end
+                int prev = -1, cur = v, L = 1;
+                if (mv == 1) {
+                    for (;;) {
+                        const int nx = hnext(cur, prev);
+                        prev = cur;
+                        cur = nx;
+                        ++L;
+                        if (M.md[cur] <= 1) break;
+                    }
+                }
+                if (mv == 0 || v < cur) atomicAdd(&hp[L], 1);
+            } else {  // on a cycle if the walk comes back to v without meeting an end
+                int prev = v, cur = hnext(v, -1), L = 1, mn = v;
+                bool cyc = true;
+                while (cur != v) {
+                    if (M.md[cur] <= 1) { cyc = false; break; }
+                    mn = cur < mn ? cur : mn;
+                    const int nx = hnext(cur, prev);
+                    prev = cur;
+                    cur = nx;
+                    ++L;
+                }
+                if (cyc && mn == v) atomicAdd(&hcy[L], 1);
+            }
+        }
+        wave_sync();
+        // the histograms move to md / vl (component length L at index L - 1,
+        // L <= pc <= 64 W) so that pq can hold the product's coefficients
+        for (int L = 1 + lane; L <= pc; L += 64) {
+            M.md[L - 1] = (int16_t)hp[L];
+            M.vl[L - 1] = (int16_t)hcy[L];
+        }
+        wave_sync();
+        // coefficient j = lane + 64 q of the running product lives at poly[j]
+        // (degrees 0..l, l <= 255); a coefficient that reached 2^128 is
+        // flagged in the wave-uniform bit set fl and stays flagged, since
+        // every factor has positive coefficients up to its degree
+        u128* poly = reinterpret_cast<u128*>(&M.pq[0][0]);
+        const int Q = (l >> 6) + 1;
+#pragma unroll
+        for (int q = 0; q < W; ++q)
+            if (q < Q) poly[lane + 64 * q] = (lane + 64 * q == 0) ? (u128)1 : (u128)0;
+        uint64_t fl[W];
+#pragma unroll
+        for (int q = 0; q < W; ++q) fl[q] = 0;
+        wave_sync();
+        auto flagged = [&](int j) -> bool {
+            bool f = false;
+#pragma unroll
+            for (int q = 0; q < W; ++q)
+                if ((j >> 6) == q) f = (fl[q] >> (j & 63)) & 1;
+            return f;
+        };
+        // poly <- poly * sum_{i <= deg} coef(i) x^i, truncated at degree l
+        auto mulpoly = [&](int deg, auto coef) {
+            u128 nr[W];
+            bool no[W];
+#pragma unroll
+            for (int q = 0; q < W; ++q) { nr[q] = 0; no[q] = false; }
+            const int imax = deg < l ? deg : l;
+            for (int i = 0; i <= imax; ++i) {
+                bool co = false;
+                const u128 c = coef(i, co);
+#pragma unroll
+                for (int q = 0; q < W; ++q) {
+                    const int j = lane + 64 * q;
+                    if (q >= Q || j > l || j < i || no[q]) continue;
+                    if (flagged(j - i)) { no[q] = true; continue; }
+                    const u128 o = poly[j - i];
+                    if (!o) continue;
+                    if (co) { no[q] = true; continue; }
+                    bool mo = false;
+                    const u128 t = mul128(c, o, mo);
+                    nr[q] += t;
+                    no[q] = mo || nr[q] < t;
+                }
+            }
+            wave_sync();
+#pragma unroll
+            for (int q = 0; q < W; ++q) {
+                if (q < Q) poly[lane + 64 * q] = nr[q];
+                fl[q] |= uni64(__ballot(no[q]));
+            }
+            wave_sync();
+        };
+        for (int L = 1; L <= pc; ++L) {
+            const int np = M.md[L - 1], nc = M.vl[L - 1];
+            if (np && L == 1) {
+                mulpoly(np, [&](int i, bool& o) { return binom128(np, i, o); });
+            } else if (np && L == 2) {
+                mulpoly(np, [&](int i, bool& o) {
+                    if (i >= 128) { o = true; return (u128)0; }
+                    return mul128(binom128(np, i, o), (u128)1 << i, o);
+                });
+            } else {
+                for (int rep = 0; rep < np; ++rep)
+                    mulpoly((L + 1) / 2, [&](int i, bool& o) { return binom128(L - i + 1, i, o); });
+            }
+            for (int rep = 0; rep < nc; ++rep)
+                mulpoly(L / 2, [&](int i, bool& o) {
+                    if (i == 0) return (u128)1;
+                    const u128 x = binom128(L - i, i, o), y = binom128(L - i - 1, i - 1, o);
+                    if (x + y < x) o = true;
+                    return x + y;
+                });
+        }
+        ovf |= flagged(l);
+        const u128 res = poly[l];
+        wave_sync();
+        return res;
+}
+
 }  // namespace
 
 template <int W, bool LIST>
@@ -226,7 +419,7 @@ __global__ __launch_bounds__(256, (W <= 3 ? 3 : 2)) void k_search(SearchArgs a) 
     auto FR = [&](int d) -> Frame<W>& { return d < LDS_FRAMES ? M.fr[d] : gfr[d - LDS_FRAMES]; };
     const int lane = lane_id();
     const int opts = a.opts;
-    const bool rule1 = opts & OPT_RULE1, rule2 = opts & OPT_RULE2, et = opts & OPT_ET, t2 = opts & OPT_TPLEX2;
+    const bool rule1 = opts & OPT_RULE1, rule2 = opts & OPT_RULE2, et = opts & OPT_ET;
     const bool work = opts & OPT_WORK;
     Acc acc{0, false};
     uint64_t wk_tasks = 0, wk_nodes = 0, wk_ops = 0;
@@ -243,6 +436,10 @@ __global__ __launch_bounds__(256, (W <= 3 ? 3 : 2)) void k_search(SearchArgs a) 
         const ArenaView& A = a.views ? a.views[gi] : a.A;
         const int k = a.graph_k ? uniform_i32(a.graph_k[gi]) : a.k;
         const int c = uniform_i32(A.seed_c[slot]);
+        // t of the closed forms: fixed, or 2 when 2k <= tau and 3 above (Section 6.1)
+        const int tau_g = a.graph_tau ? uniform_i32(a.graph_tau[gi]) : a.tau;
+        const int tpl = a.tplex > 0 ? a.tplex : (2 * k <= tau_g ? 2 : 3);
+        const bool t2 = et && tpl >= 2, t3 = et && tpl >= 3;
         const int64_t ro = A.row_off[slot], vo = A.vtx_off[slot];
         wk_tasks += work;
         Acc tacc{0, false};
@@ -305,6 +502,11 @@ __global__ __launch_bounds__(256, (W <= 3 ? 3 : 2)) void k_search(SearchArgs a) 
                 if (t2 && mind >= pc - 2) {
                     const int nfull = (int)wsum_u32((uint32_t)nf);
                     val = twoplex_count(nfull, (pc - nfull) / 2, l, tacc.ovf);
+                    return true;
+                }
+                if (l == pc) { val = 0; return true; }  // P itself is not a clique
+                if (t3 && mind >= pc - 3) {
+                    val = threeplex_count<W>(M, P, pc, l, tacc.ovf);
                     return true;
                 }
             }
@@ -612,9 +814,11 @@ __global__ __launch_bounds__(256, (W <= 3 ? 3 : 2)) void k_search(SearchArgs a) 
             active = !finish(P0, l0, rootval);
             if (!active) tacc.add(rootval);
         } else if (et && l0 >= 3) {
-            // a root split over several tasks that is a clique: this task's
-            // part is the l0-cliques whose first vertex x lies in [x0, x1),
-            // sum_x C(c-1-x, l0-1)
+            // a root split over several tasks that is a clique, 2-plex or
+            // 3-plex (as far as t allows): this task's part is the
+            // l0-cliques whose first vertex x lies in [x0, x1), for a clique
+            // sum_x C(c-1-x, l0-1), else the closed form of each later
+            // neighbourhood P0 & N+(x) (a t-plex again) at l0 - 1
             int mn = 1 << 30;
 #pragma unroll
             for (int q = 0; q < W; ++q) {
@@ -626,12 +830,28 @@ __global__ __launch_bounds__(256, (W <= 3 ? 3 : 2)) void k_search(SearchArgs a) 
                     mn = d < mn ? d : mn;
                 }
             }
-            if (wmin_i32(mn) >= c - 1) {
+            const int mind = wmin_i32(mn);
+            const int xe = x1 < c ? x1 : c;
+            if (mind >= c - 1) {
                 u128 part = 0;
-                const int xe = x1 < c ? x1 : c;
                 for (int x = x0; x < xe; ++x) part += binom128(c - 1 - x, l0 - 1, tacc.ovf);
                 tacc.add(part);
                 active = false;
+            } else if (mind >= c - tpl) {
+                u128 part = 0;
+                bool all = true;
+                for (int x = x0; x < xe && all; ++x) {
+                    uint64_t Rx[W];
+#pragma unroll
+                    for (int w = 0; w < W; ++w) Rx[w] = uni64(P0[w] & M.rows[x][w] & upper_mask(x, w));
+                    u128 v = 0;
+                    all = finish(Rx, l0 - 1, v);
+                    part += v;
+                }
+                if (all) {
+                    tacc.add(part);
+                    active = false;
+                }
             }
         }
         if (active && (l0 == 4 || l0 == 5)) {
@@ -838,6 +1058,7 @@ float k4_weight_of(int32_t dense_k4) { return dense_k4 < 0 ? 0.f : (dense_k4 == 
 
 hipError_t launch_binom_init(hipStream_t s) {
     hipLaunchKernelGGL(k_binom_init, dim3((BIN_N + 255) / 256), dim3(256), 0, s);
+    hipLaunchKernelGGL(k_binom128_init, dim3(1), dim3(64), 0, s);
     return hipGetLastError();
 }
 

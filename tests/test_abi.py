@@ -37,7 +37,7 @@ def test_strerror_and_defaults_without_gpu():
         pytest.skip("libebbkc.so not built")
     assert ebb.ebbkc_strerror(ebb.E_BAD_CSR).startswith("input is not")
     o = ebb.ebbkc_default_options()
-    assert (o.early_termination, o.t_plex, o.rule1, o.rule2) == (1, 2, 1, 1)
+    assert (o.early_termination, o.t_plex, o.rule1, o.rule2) == (1, 0, 1, 1)
 
 
 def test_product_path_does_not_reference_the_oracle():
