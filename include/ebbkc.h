@@ -82,8 +82,24 @@ typedef struct {
     int32_t dense_k4;          /* 4-cliques of a dense candidate set counted from its missing pairs
                                   when that costs less than branching: weight (percent) of its cost
                                   estimate, 0 = default (100), < 0 = never */
-    int32_t reserved[6];
+    int32_t ordering;          /* edge order of the initial branch and colouring below it:
+                                  EBBKC_ORDER_HYBRID (0, default): truss-based order at the
+                                    initial branch, each g_i coloured on its own (EBBkC-H,
+                                    Section 4.4);
+                                  EBBKC_ORDER_COLOR (1): one greedy colouring of G, vertices by
+                                    non-increasing colour, edges in the lexicographic order of
+                                    their endpoints' positions; every g_i keeps G's colours
+                                    (EBBkC-C, Section 4.3);
+                                  EBBKC_ORDER_DEGEN_VERTEX (2): vertices in a degeneracy order,
+                                    edges in the lexicographic order of their endpoints'
+                                    positions, each g_i coloured on its own: vertex-oriented
+                                    branching (Algorithm VBBkC, degeneracy order) with its first
+                                    two steps taken together, the edge-parallel scheme of
+                                    Section 6.2 (7).  Other values: EBBKC_E_INVALID_ARG. */
+    int32_t reserved[5];
 } ebbkc_options;
+
+enum { EBBKC_ORDER_HYBRID = 0, EBBKC_ORDER_COLOR = 1, EBBKC_ORDER_DEGEN_VERTEX = 2 };
 
 typedef struct {
     int32_t n;          /* vertices */
@@ -102,9 +118,14 @@ enum {
 /* Array selectors for ebbkc_export. */
 enum {
     EBBKC_ARR_SUPPORT = 0, /* int32[m]: common neighbours of each edge in G */
-    EBBKC_ARR_RANK = 1,    /* int32[m]: position of each edge in pi_tau */
+    EBBKC_ARR_RANK = 1,    /* int32[m]: position of each edge in the initial branch's edge order
+                              (pi_tau under the default ordering) */
     EBBKC_ARR_LEVEL = 2,   /* int32[m]: truss level of each edge */
-    EBBKC_ARR_SUBSIZE = 3  /* int32[m]: |V(g_i)| of each edge's sub-branch */
+    EBBKC_ARR_SUBSIZE = 3, /* int32[m]: |V(g_i)| of each edge's sub-branch */
+    EBBKC_ARR_VERTEX_POS = 4,   /* int32[n]: position of each vertex in the vertex order the
+                                   edge ranks follow (orderings COLOR and DEGEN_VERTEX only) */
+    EBBKC_ARR_VERTEX_COLOR = 5  /* int32[n]: colour (1, 2, ...) of each vertex in the greedy
+                                   colouring of G (ordering COLOR only) */
 };
 
 void ebbkc_default_options(ebbkc_options *opt);
@@ -161,8 +182,9 @@ ebbkc_status ebbkc_list(ebbkc_graph *g, int32_t k, int64_t r_begin, int64_t r_en
                         uint64_t cap, uint32_t flags, uint64_t *out_written,
                         uint64_t *out_checksums, void *stream);
 
-/* Copy one per-edge array (EBBKC_ARR_*) into dst (int32[m], host or device
- * per ptr_kind). */
+/* Copy one array (EBBKC_ARR_*) into dst (int32[m] for the per-edge arrays,
+ * int32[n] for the per-vertex ones; host or device per ptr_kind).  A
+ * per-vertex array the handle's ordering does not hold: EBBKC_E_INVALID_ARG. */
 ebbkc_status ebbkc_export(const ebbkc_graph *g, int32_t which, int32_t *dst, int32_t ptr_kind,
                           void *stream);
 

@@ -20,7 +20,8 @@ OK, E_INVALID_ARG, E_BAD_CSR, E_OOM, E_K_RANGE, E_BUFFER_TOO_SMALL, E_OVERFLOW, 
     0, -1, -2, -3, -4, -5, -6, -7, -8, -9)
 PTR_HOST, PTR_DEVICE = 0, 1
 LIST_SORTED = 1
-ARR_SUPPORT, ARR_RANK, ARR_LEVEL, ARR_SUBSIZE = 0, 1, 2, 3
+ARR_SUPPORT, ARR_RANK, ARR_LEVEL, ARR_SUBSIZE, ARR_VERTEX_POS, ARR_VERTEX_COLOR = 0, 1, 2, 3, 4, 5
+ORDER_HYBRID, ORDER_COLOR, ORDER_DEGEN_VERTEX = 0, 1, 2
 
 
 class EbbkcError(RuntimeError):
@@ -33,7 +34,7 @@ class ebbkc_options(ctypes.Structure):
     _fields_ = [("early_termination", ctypes.c_int32), ("t_plex", ctypes.c_int32), ("rule1", ctypes.c_int32),
                 ("rule2", ctypes.c_int32), ("waves_per_block", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
                 ("split_threshold", ctypes.c_int32), ("count_work", ctypes.c_int32),
-                ("dense_k4", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6)]
+                ("dense_k4", ctypes.c_int32), ("ordering", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
 
 
 class ebbkc_result(ctypes.Structure):
@@ -385,9 +386,10 @@ class Graph:
         return ebbkc_count_range(self._h, k, r_begin, r_end)
 
     def export(self, which: int) -> np.ndarray:
-        out = np.zeros(max(int(self.info.m), 1), np.int32)
+        size = int(self.info.n) if which in (ARR_VERTEX_POS, ARR_VERTEX_COLOR) else int(self.info.m)
+        out = np.zeros(max(size, 1), np.int32)
         ebbkc_export(self._h, which, out)
-        return out[: int(self.info.m)]
+        return out[:size]
 
     def last_timing(self):
         return ebbkc_last_timing(self._h)

@@ -42,7 +42,7 @@ void ebbkc_destroy(ebbkc_graph* g) {
     (void)hipSetDevice(g->device);
     void* ptrs[] = {g->rp, g->ci, g->erank, g->eu, g->ev, g->sup0, g->rank, g->level, g->rrow, g->orp, g->orow,
                     g->byrank, g->subsize, g->scratch, g->d_counters, g->seed_eid, g->seed_c, g->row_off,
-                    g->vtx_off, g->arows, g->agid, g->acol, g->nedges};
+                    g->vtx_off, g->arows, g->agid, g->acol, g->nedges, g->vpos, g->vcol};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (g->h_counters) (void)hipHostFree(g->h_counters);
@@ -62,6 +62,10 @@ ebbkc_status ebbkc_prepare(const int32_t* row_ptr, const int32_t* col_idx, int32
     if (hipGetDeviceProperties(&prop, g->device) != hipSuccess) { delete g; return EBBKC_E_HIP; }
     g->cu_count = prop.multiProcessorCount;
     if (opt) g->opt = *opt; else ebbkc_default_options(&g->opt);
+    if (g->opt.ordering < EBBKC_ORDER_HYBRID || g->opt.ordering > EBBKC_ORDER_DEGEN_VERTEX) {
+        delete g;
+        return EBBKC_E_INVALID_ARG;
+    }
     g->n = n;
     g->nnz = nnz;
     ebbkc_status st = ebb::prepare_impl(g, row_ptr, col_idx, ptr_kind, (hipStream_t)stream);
@@ -156,11 +160,16 @@ ebbkc_status ebbkc_export(const ebbkc_graph* gc, int32_t which, int32_t* dst, in
             src = g->subsize;
             break;
         }
+        case EBBKC_ARR_VERTEX_POS: src = g->vpos; break;
+        case EBBKC_ARR_VERTEX_COLOR: src = g->vcol; break;
         default: return EBBKC_E_INVALID_ARG;
     }
-    if (g->m == 0) return EBBKC_OK;
+    const bool per_vertex = which == EBBKC_ARR_VERTEX_POS || which == EBBKC_ARR_VERTEX_COLOR;
+    const int64_t len = per_vertex ? (int64_t)g->n : g->m;
+    if (len == 0) return EBBKC_OK;
+    if (!src) return EBBKC_E_INVALID_ARG;  // not held under this handle's ordering
     hipMemcpyKind kind = ptr_kind == EBBKC_PTR_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
-    if (hipMemcpyAsync(dst, src, sizeof(int32_t) * (size_t)g->m, kind, s) != hipSuccess) return EBBKC_E_HIP;
+    if (hipMemcpyAsync(dst, src, sizeof(int32_t) * (size_t)len, kind, s) != hipSuccess) return EBBKC_E_HIP;
     if (hipStreamSynchronize(s) != hipSuccess) return EBBKC_E_HIP;
     return EBBKC_OK;
 }

@@ -52,6 +52,7 @@ struct BuildArgs {
     int32_t* gid;
     int16_t* col;
     uint64_t* nedges;  // edges of g_i per slot
+    const int32_t* vcol;  // colours of G kept in every g_i, or null: each g_i coloured on its own
     unsigned long long* next;
     int* err;
 };

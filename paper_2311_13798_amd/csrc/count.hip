@@ -292,6 +292,7 @@ ebbkc_status arena_impl(ebbkc_graph* g, hipStream_t s) {
         b.gid = gid.p;
         b.col = col.p;
         b.nedges = ned.p;
+        b.vcol = g->opt.ordering == EBBKC_ORDER_COLOR ? g->vcol : nullptr;
         b.next = (unsigned long long*)(g->d_counters + W - 1);
         b.err = err;
         CHKH(launch_build(W, b, g->cu_count, s));

@@ -20,6 +20,7 @@
 #include <vector>
 
 #include "common.h"
+#include "device_util.h"
 #include "handle.h"
 #include "prims.h"
 
@@ -298,6 +299,117 @@ __global__ void k_level_by_rank(const int32_t* __restrict__ byrank, const int32_
         out[i] = level[byrank[i]];
 }
 
+// ---- vertex orders for the root edge order of the ablation orderings
+
+// Greedy colouring in the visiting order (degree desc, id asc), one wave per
+// vertex: a vertex takes the least colour >= 1 not held by its neighbours
+// earlier in that order once all of them are coloured, which is the colour
+// the sequential greedy pass gives it (Jones-Plassmann rounds).  A vertex
+// still waiting adds one to *pending.
+constexpr int CWIN = 4096;  // colours tested per window
+
+__device__ __forceinline__ bool visits_before(int32_t w, int32_t dw, int32_t v, int32_t dv) {
+    return dw > dv || (dw == dv && w < v);
+}
+
+__global__ __launch_bounds__(TB) void k_colour_round(const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                                                     int32_t n, int32_t* col, int32_t* __restrict__ pending) {
+    __shared__ uint32_t used[TB / EBB_WAVE][CWIN / 32];
+    const int lane = lane_id(), wv = threadIdx.x / EBB_WAVE;
+    const int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / EBB_WAVE;
+    const int64_t nw = (int64_t)gridDim.x * blockDim.x / EBB_WAVE;
+    const volatile int32_t* vcol = col;
+    int waiting = 0;
+    for (int64_t vv = wid; vv < n; vv += nw) {
+        const int32_t v = (int32_t)vv;
+        if (__builtin_amdgcn_readfirstlane(vcol[v]) != 0) continue;
+        const int32_t b = rp[v], e = rp[v + 1], dv = e - b;
+        bool wait = false;
+        for (int32_t j = b + lane; j < e; j += EBB_WAVE) {
+            const int32_t w = ci[j];
+            if (visits_before(w, rp[w + 1] - rp[w], v, dv) && vcol[w] == 0) wait = true;
+        }
+        if (ballot(wait)) { ++waiting; continue; }
+        // the least colour absent from the earlier neighbours (at most dv of them)
+        for (int32_t base = 1;; base += CWIN) {
+            for (int i = lane; i < CWIN / 32; i += EBB_WAVE) used[wv][i] = 0;
+            wave_sync();
+            for (int32_t j = b + lane; j < e; j += EBB_WAVE) {
+                const int32_t w = ci[j];
+                if (!visits_before(w, rp[w + 1] - rp[w], v, dv)) continue;
+                const int32_t cw = vcol[w] - base;
+                if (cw >= 0 && cw < CWIN) atomicOr(&used[wv][cw >> 5], 1u << (cw & 31));
+            }
+            wave_sync();
+            int first = CWIN;
+            for (int i = lane; i < CWIN / 32; i += EBB_WAVE) {
+                const uint32_t f = ~used[wv][i];
+                if (f) { first = i * 32 + __builtin_ctz(f); break; }
+            }
+            first = wave_min(first);
+            wave_sync();
+            if (first < CWIN) {
+                if (lane == 0) col[v] = base + first;
+                break;
+            }
+        }
+    }
+    if (lane == 0 && waiting) atomicAdd(pending, waiting);
+}
+
+// colour order: key (colour desc), vertex id as the value; a stable sort keeps ids ascending
+__global__ void k_colour_keys(const int32_t* __restrict__ col, int32_t n, uint64_t* __restrict__ keys,
+                              uint32_t* __restrict__ vals) {
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+        keys[v] = (uint64_t)(0x7fffffff - col[v]);
+        vals[v] = (uint32_t)v;
+    }
+}
+
+__global__ void k_scatter_pos(const uint32_t* __restrict__ vals, int64_t n, int32_t* __restrict__ pos) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        pos[vals[i]] = (int32_t)i;
+}
+
+__global__ void k_degrees(const int32_t* __restrict__ rp, int32_t n, int32_t* __restrict__ deg) {
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+        deg[v] = rp[v + 1] - rp[v];
+}
+
+__global__ void k_core_assign(const int32_t* __restrict__ front, int64_t nf, int64_t placed, int32_t r,
+                              int32_t* __restrict__ pos, int32_t* __restrict__ rnd) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nf; i += (int64_t)gridDim.x * blockDim.x) {
+        pos[front[i]] = (int32_t)(placed + i);
+        rnd[front[i]] = r;
+    }
+}
+
+// one wave per removed vertex: its neighbours still present lose one degree
+__global__ void k_core_remove(const int32_t* __restrict__ front, int64_t nf, const int32_t* __restrict__ rp,
+                              const int32_t* __restrict__ ci, const int32_t* __restrict__ rnd,
+                              int32_t* __restrict__ deg) {
+    const int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / EBB_WAVE;
+    const int64_t nw = (int64_t)gridDim.x * blockDim.x / EBB_WAVE;
+    for (int64_t i = wid; i < nf; i += nw) {
+        const int32_t v = front[i];
+        for (int32_t j = rp[v] + lane_id(); j < rp[v + 1]; j += EBB_WAVE) {
+            const int32_t w = ci[j];
+            if (rnd[w] < 0) atomicSub(&deg[w], 1);
+        }
+    }
+}
+
+// edge e = (u, v): key (min pos, max pos), lexicographic
+__global__ void k_lex_edge_keys(const int32_t* __restrict__ eu, const int32_t* __restrict__ ev,
+                                const int32_t* __restrict__ pos, int64_t m, int32_t n, uint64_t* __restrict__ keys,
+                                uint32_t* __restrict__ vals) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t a = pos[eu[e]], b = pos[ev[e]];
+        keys[e] = (uint64_t)(a < b ? a : b) * (uint64_t)n + (uint64_t)(a < b ? b : a);
+        vals[e] = (uint32_t)e;
+    }
+}
+
 __global__ void k_copy_i64_to_i32(const int64_t* __restrict__ a, int32_t* __restrict__ b, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         b[i] = (int32_t)a[i];
@@ -484,6 +596,97 @@ ebbkc_status prepare_impl(ebbkc_graph* g, const int32_t* row_ptr, const int32_t*
     g->tau = maxlev;
     g->rounds = r;
 
+    // ---- root edge order from a vertex order (ablation orderings): edges in the
+    // lexicographic order of their endpoints' positions replace pi_tau; levels
+    // and tau stay those of the truss peel (tau + 2 still bounds the clique size)
+    if (g->opt.ordering != EBBKC_ORDER_HYBRID && n > 0) {
+        const int64_t big = (int64_t)n > m ? (int64_t)n : m;
+        DBuf<int32_t> vpos, vcol;
+        DBuf<uint64_t> k1, k2;
+        DBuf<uint32_t> v1, v2;
+        DBuf<int64_t> rh, rht;
+        CHK(vpos.alloc(n));
+        CHK(k1.alloc(big));
+        CHK(k2.alloc(big));
+        CHK(v1.alloc(big));
+        CHK(v2.alloc(big));
+        const int64_t rhn = radix_hist_elems(big);
+        CHK(rh.alloc(rhn));
+        CHK(rht.alloc(scan_tmp_elems(rhn) + 16));
+        if (g->opt.ordering == EBBKC_ORDER_COLOR) {
+            // greedy colouring (Section 4.3), then vertices by colour desc, id asc
+            CHK(vcol.alloc(n));
+            CHK(hipMemsetAsync(vcol.p, 0, sizeof(int32_t) * (size_t)n, s));
+            unsigned gc = grid_for((int64_t)n * EBB_WAVE);
+            if (gc > 16384) gc = 16384;
+            for (;;) {
+                CHK(hipMemsetAsync(dstat + 2, 0, sizeof(int), s));
+                hipLaunchKernelGGL(k_colour_round, dim3(gc), dim3(TB), 0, s, rp.p, ci.p, n, vcol.p, dstat + 2);
+                CHK(hipGetLastError());
+                CHK(hipMemcpyAsync(hstat + 2, dstat + 2, sizeof(int), hipMemcpyDeviceToHost, s));
+                CHK(hipStreamSynchronize(s));
+                if (hstat[2] == 0) break;
+            }
+            hipLaunchKernelGGL(k_colour_keys, dim3(grid_for(n)), dim3(TB), 0, s, vcol.p, n, k1.p, v1.p);
+            CHK(radix_sort_u64(k1.p, v1.p, k2.p, v2.p, n, 31, rh.p, rht.p, s));
+            hipLaunchKernelGGL(k_scatter_pos, dim3(grid_for(n)), dim3(TB), 0, s, v1.p, (int64_t)n, vpos.p);
+            CHK(hipGetLastError());
+        } else {
+            // degeneracy order, level-synchronous: at level s every remaining
+            // vertex of degree <= s leaves in one round, placed by (round, id)
+            DBuf<int32_t> deg, vlive, vkeep, vfront, vflag, vrnd;
+            DBuf<int64_t> vps;
+            CHK(deg.alloc(n));
+            CHK(vlive.alloc(n));
+            CHK(vkeep.alloc(n));
+            CHK(vfront.alloc(n));
+            CHK(vflag.alloc(n));
+            CHK(vrnd.alloc(n));
+            CHK(vps.alloc(n + 1));
+            hipLaunchKernelGGL(k_degrees, dim3(grid_for(n)), dim3(TB), 0, s, rp.p, n, deg.p);
+            hipLaunchKernelGGL(k_iota, dim3(grid_for(n)), dim3(TB), 0, s, vlive.p, (int64_t)n);
+            hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(n)), dim3(TB), 0, s, vrnd.p, (int64_t)n, -1);
+            CHK(hipGetLastError());
+            int64_t nl = n, placed = 0;
+            int32_t lv = 0, rr = 0;
+            while (placed < n) {
+                unsigned gl = grid_for(nl, TB * 8);
+                if (gl > 2048) gl = 2048;
+                hipLaunchKernelGGL(k_peel_reset, dim3(1), dim3(1), 0, s, st.p);
+                hipLaunchKernelGGL(k_peel_flag, dim3(gl), dim3(TB), 0, s, vlive.p, nl, deg.p, lv, vflag.p, st.p);
+                CHK(exclusive_scan_i32(vflag.p, vps.p, nl, &st.p->nf, scan_tmp.p, s));
+                CHK(hipMemcpyAsync(hst, st.p, sizeof(PeelState), hipMemcpyDeviceToHost, s));
+                CHK(hipStreamSynchronize(s));
+                const int64_t nf = hst->nf;
+                if (nf == 0) {
+                    lv = hst->minsup;
+                    continue;
+                }
+                hipLaunchKernelGGL(k_peel_compact, dim3(gl), dim3(TB), 0, s, vlive.p, nl, vflag.p, vps.p, vfront.p,
+                                   vkeep.p);
+                hipLaunchKernelGGL(k_core_assign, dim3(grid_for(nf)), dim3(TB), 0, s, vfront.p, nf, placed, rr,
+                                   vpos.p, vrnd.p);
+                unsigned gw = grid_for(nf * EBB_WAVE);
+                if (gw > 16384) gw = 16384;
+                hipLaunchKernelGGL(k_core_remove, dim3(gw), dim3(TB), 0, s, vfront.p, nf, rp.p, ci.p, vrnd.p, deg.p);
+                CHK(hipGetLastError());
+                placed += nf;
+                nl -= nf;
+                ++rr;
+                int32_t* t = vlive.p; vlive.p = vkeep.p; vkeep.p = t;
+            }
+        }
+        if (m) {
+            hipLaunchKernelGGL(k_lex_edge_keys, dim3(grid_for(m)), dim3(TB), 0, s, eu.p, ev.p, vpos.p, m, n, k1.p,
+                               v1.p);
+            CHK(radix_sort_u64(k1.p, v1.p, k2.p, v2.p, m, bits_for((uint64_t)n * (uint64_t)n), rh.p, rht.p, s));
+            hipLaunchKernelGGL(k_scatter_pos, dim3(grid_for(m)), dim3(TB), 0, s, v1.p, m, rank.p);
+            CHK(hipGetLastError());
+        }
+        g->vpos = vpos.release();
+        g->vcol = vcol.release();
+    }
+
     // ---- rank-tagged adjacency
     DBuf<int32_t> erank;
     DBuf<uint64_t> keys, keys2;
@@ -543,7 +746,8 @@ ebbkc_status prepare_impl(ebbkc_graph* g, const int32_t* row_ptr, const int32_t*
     g->orp = orp.release();
     g->orow = orow.release();
     g->byrank = byrank.release();
-    g->device_bytes = (int64_t)sizeof(int32_t) * ((n + 1) * 2 + nnz * 2 + m * 6) + (int64_t)sizeof(int2) * (nnz + m);
+    g->device_bytes = (int64_t)sizeof(int32_t) * ((n + 1) * 2 + nnz * 2 + m * 6) + (int64_t)sizeof(int2) * (nnz + m) +
+                      (int64_t)sizeof(int32_t) * n * ((g->vpos ? 1 : 0) + (g->vcol ? 1 : 0));
     return EBBKC_OK;
 }
 

@@ -15,6 +15,8 @@
 //                  id; then vertices are relabelled by non-increasing colour,
 //                  ties to the smaller vertex id (Section 4.3; Algorithm
 //                  EBBkC-H colours each g_i and orients it by this order).
+//                  Under EBBkC-C the colours of G's own colouring are kept
+//                  instead (renumbered 1..D among the colours present).
 // The relabelled symmetric rows, colours and global ids go to the seed's
 // arena slot; the search kernels orient them low -> high.
 #include "arena.h"
@@ -215,53 +217,89 @@ __global__ __launch_bounds__(256) void k_build(BuildArgs a) {
         }
         dsum = wave_sum(dsum);
         wave_sync();
-#pragma unroll
-        for (int q = 0; q < W; ++q) {
-            const int i = lane + 64 * q;
-            const int di = i < c ? M.key[i] : 0, gi = i < c ? M.gid[i] : 0;
-            int ord = 0;
-            for (int j = 0; j < c; ++j) {
-                const int dj = M.key[j], gj = M.gid[j];
-                ord += (dj > di) || (dj == di && gj < gi);
-            }
-            if (i < c) M.seq[ord] = (int16_t)i;
-        }
-        wave_sync();
-        // ---- 3b. greedy colouring; colour-class masks live in lanes
-        uint64_t cls[W][W];
-#pragma unroll
-        for (int q = 0; q < W; ++q)
-#pragma unroll
-            for (int w = 0; w < W; ++w) cls[q][w] = 0;
-        int ncol = 0;
-        for (int t = 0; t < c; ++t) {
-            const int i = M.seq[t];
-            uint64_t A[W];
-#pragma unroll
-            for (int w = 0; w < W; ++w) A[w] = M.rows[i][w];
-            int found = -1;
+        if (a.vcol) {
+            // ---- 3'. G's colouring kept (EBBkC-C): the colours present are
+            // renumbered 1..D in their order, which changes neither the order
+            // below nor the number of colours in any vertex set
+            for (int i = lane; i < c; i += 64) M.key[i] = a.vcol[M.gid[i]];
+            wave_sync();
 #pragma unroll
             for (int q = 0; q < W; ++q) {
-                bool ok = lane + 64 * q < ncol;
-#pragma unroll
-                for (int w = 0; w < W; ++w) ok = ok && ((cls[q][w] & A[w]) == 0);
-                const uint64_t mk = ballot(ok);
-                if (found < 0 && mk) found = 64 * q + __builtin_ctzll(mk);
+                const int i = lane + 64 * q;
+                const int ki = i < c ? M.key[i] : 0, gi = i < c ? M.gid[i] : 0;
+                int ord = 0;
+                for (int j = 0; j < c; ++j) {
+                    const int kj = M.key[j], gj = M.gid[j];
+                    ord += (kj > ki) || (kj == ki && gj < gi);
+                }
+                if (i < c) M.seq[ord] = (int16_t)i;
             }
-            if (found < 0) found = ncol++;
-            found = uniform_i32(found);
-            if (lane == (found & 63)) {
+            wave_sync();
+            int cum[W];
+            int starts = 0;
 #pragma unroll
-                for (int q = 0; q < W; ++q)
-                    if (q == (found >> 6)) {
-#pragma unroll
-                        for (int w = 0; w < W; ++w)
-                            if (w == (i >> 6)) cls[q][w] |= 1ull << (i & 63);
-                    }
+            for (int q = 0; q < W; ++q) {
+                const int p = lane + 64 * q;
+                const bool st = p < c && (p == 0 || M.key[M.seq[p]] != M.key[M.seq[p - 1]]);
+                const uint64_t mk = ballot(st);
+                cum[q] = starts + popc64(mk & (lanemask_lt() | (1ull << lane)));
+                starts += popc64(mk);
             }
-            if (lane == 0) M.col[i] = (int16_t)(found + 1);
+#pragma unroll
+            for (int q = 0; q < W; ++q) {
+                const int p = lane + 64 * q;
+                if (p < c) M.col[M.seq[p]] = (int16_t)(starts - cum[q] + 1);
+            }
+            wave_sync();
+        } else {
+#pragma unroll
+            for (int q = 0; q < W; ++q) {
+                const int i = lane + 64 * q;
+                const int di = i < c ? M.key[i] : 0, gi = i < c ? M.gid[i] : 0;
+                int ord = 0;
+                for (int j = 0; j < c; ++j) {
+                    const int dj = M.key[j], gj = M.gid[j];
+                    ord += (dj > di) || (dj == di && gj < gi);
+                }
+                if (i < c) M.seq[ord] = (int16_t)i;
+            }
+            wave_sync();
+            // ---- 3b. greedy colouring; colour-class masks live in lanes
+            uint64_t cls[W][W];
+#pragma unroll
+            for (int q = 0; q < W; ++q)
+#pragma unroll
+                for (int w = 0; w < W; ++w) cls[q][w] = 0;
+            int ncol = 0;
+            for (int t = 0; t < c; ++t) {
+                const int i = M.seq[t];
+                uint64_t A[W];
+#pragma unroll
+                for (int w = 0; w < W; ++w) A[w] = M.rows[i][w];
+                int found = -1;
+#pragma unroll
+                for (int q = 0; q < W; ++q) {
+                    bool ok = lane + 64 * q < ncol;
+#pragma unroll
+                    for (int w = 0; w < W; ++w) ok = ok && ((cls[q][w] & A[w]) == 0);
+                    const uint64_t mk = ballot(ok);
+                    if (found < 0 && mk) found = 64 * q + __builtin_ctzll(mk);
+                }
+                if (found < 0) found = ncol++;
+                found = uniform_i32(found);
+                if (lane == (found & 63)) {
+#pragma unroll
+                    for (int q = 0; q < W; ++q)
+                        if (q == (found >> 6)) {
+#pragma unroll
+                            for (int w = 0; w < W; ++w)
+                                if (w == (i >> 6)) cls[q][w] |= 1ull << (i & 63);
+                        }
+                }
+                if (lane == 0) M.col[i] = (int16_t)(found + 1);
+            }
+            wave_sync();
         }
-        wave_sync();
         // ---- 3c. relabel by colour desc, id asc, and write the slot
         int npos[W];
 #pragma unroll

@@ -37,7 +37,29 @@ def test_strerror_and_defaults_without_gpu():
         pytest.skip("libebbkc.so not built")
     assert ebb.ebbkc_strerror(ebb.E_BAD_CSR).startswith("input is not")
     o = ebb.ebbkc_default_options()
-    assert (o.early_termination, o.t_plex, o.rule1, o.rule2) == (1, 0, 1, 1)
+    assert (o.early_termination, o.t_plex, o.rule1, o.rule2, o.ordering) == (1, 0, 1, 1, 0)
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    # the ctypes mirrors of the option / info / result structs have the C sizes and offsets
+    import ctypes
+    import subprocess
+    import paper_2311_13798_amd as ebb
+    src = tmp_path / "sizes.c"
+    src.write_text('''#include <stddef.h>
+#include <stdio.h>
+#include "ebbkc.h"
+int main(void) {
+    printf("%zu %zu %zu %zu %zu\\n", sizeof(ebbkc_options), offsetof(ebbkc_options, ordering),
+           offsetof(ebbkc_options, dense_k4), sizeof(ebbkc_info), offsetof(ebbkc_info, prepare_ms));
+    return 0;
+}
+''')
+    exe = tmp_path / "sizes"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
+    O, I = ebb.ebbkc_options, ebb.ebbkc_info
+    assert got == [ctypes.sizeof(O), O.ordering.offset, O.dense_k4.offset, ctypes.sizeof(I), I.prepare_ms.offset]
 
 
 def test_product_path_does_not_reference_the_oracle():

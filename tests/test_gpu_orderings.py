@@ -1,0 +1,179 @@
+"""Initial-branch edge orders of the ablation orderings: EBBkC-C (Section 4.3: one greedy colouring
+of G, vertices by non-increasing colour, edges in the lexicographic order of their endpoints'
+positions, G's colours kept in every sub-branch) and the edge-parallel VBBkC root (Algorithm VBBkC in
+a degeneracy order with its first two branching steps taken together, Section 6.2 (7)).
+
+The vertex orders are checked against their definitions written out here (sequential greedy
+colouring, level-synchronous core peel), the edge ranks against the lexicographic rule, sub-branch
+sizes and per-seed counts against the oracle under the exported ranking, and N_k and listings
+against the oracle and the default ordering."""
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+from graphgen import configs
+
+pytestmark = pytest.mark.gpu
+
+
+def greedy_colouring(g):
+    """Sequential greedy colouring visiting vertices by (degree desc, id asc)."""
+    rp, ci = g.row_ptr, g.col_idx
+    deg = np.diff(rp)
+    col = np.zeros(g.n, np.int64)
+    for v in sorted(range(g.n), key=lambda x: (-deg[x], x)):
+        used = {int(col[w]) for w in ci[rp[v]:rp[v + 1]]}
+        c = 1
+        while c in used:
+            c += 1
+        col[v] = c
+    return col
+
+
+def core_peel_order(g):
+    """Level-synchronous core peel: at level s every remaining vertex of degree <= s leaves in one
+    round (placed in id order); s jumps to the least remaining degree when none qualifies."""
+    rp, ci = g.row_ptr, g.col_idx
+    deg = np.diff(rp).astype(np.int64)
+    alive = np.ones(g.n, bool)
+    pos = np.full(g.n, -1, np.int64)
+    placed, s = 0, 0
+    while placed < g.n:
+        front = np.flatnonzero(alive & (deg <= s))
+        if front.size == 0:
+            s = int(deg[alive].min())
+            continue
+        pos[front] = placed + np.arange(front.size)
+        placed += front.size
+        alive[front] = False
+        for v in front:
+            nb = ci[rp[v]:rp[v + 1]]
+            np.subtract.at(deg, nb[alive[nb]], 1)
+    return pos
+
+
+GRAPHS = {
+    "er2000": lambda: configs.er_small(),
+    "er_planted": lambda: graphgen.er_planted(300, 0.05, 1, 25, 25, 2),
+    "cocktail": lambda: graphgen.cocktail_party(10),
+    "rmat10": lambda: graphgen.rmat(10, 16, seed=1),
+}
+
+
+@pytest.fixture(scope="module")
+def ebb():
+    import torch
+    import paper_2311_13798_amd as m
+    torch.cuda.set_device(0)
+    m.load_library()
+    return m
+
+
+def prepared(ebb, g, ordering, **kw):
+    o = ebb.ebbkc_default_options()
+    o.ordering = ordering
+    for key, v in kw.items():
+        setattr(o, key, v)
+    return ebb.Graph.from_csr(g, options=o)
+
+
+@pytest.mark.parametrize("name", ["er2000", "er_planted", "cocktail"])
+def test_colour_order_is_the_greedy_colouring(ebb, name):
+    g = GRAPHS[name]()
+    G = prepared(ebb, g, ebb.ORDER_COLOR)
+    col = G.export(ebb.ARR_VERTEX_COLOR)
+    pos = G.export(ebb.ARR_VERTEX_POS)
+    assert np.array_equal(col, greedy_colouring(g))
+    eu, ev = oracle.edge_list(g)
+    assert (col[eu] != col[ev]).all()  # proper
+    want = sorted(range(g.n), key=lambda v: (-col[v], v))
+    assert np.array_equal(np.argsort(pos), want)
+    G.close()
+
+
+@pytest.mark.parametrize("name", ["er2000", "rmat10"])
+def test_degeneracy_order_is_the_core_peel(ebb, name):
+    g = GRAPHS[name]()
+    G = prepared(ebb, g, ebb.ORDER_DEGEN_VERTEX)
+    pos = G.export(ebb.ARR_VERTEX_POS)
+    assert np.array_equal(pos, core_peel_order(g))
+    # every vertex has at most delta neighbours later in the order (Section 3: |N+(v)| <= delta)
+    _, delta = oracle.degeneracy(g)
+    eu, ev = oracle.edge_list(g)
+    later = np.bincount(np.where(pos[eu] < pos[ev], eu, ev), minlength=g.n)
+    assert later.max() <= delta
+    with pytest.raises(ebb.EbbkcError):
+        G.export(ebb.ARR_VERTEX_COLOR)  # no colouring of G under this ordering
+    G.close()
+
+
+@pytest.mark.parametrize("ordering,name", [(1, "er2000"), (1, "er_planted"), (2, "er2000"), (2, "rmat10")])
+def test_edge_ranks_sizes_and_seed_counts(ebb, ordering, name):
+    g = GRAPHS[name]()
+    G = prepared(ebb, g, ordering)
+    pos = G.export(ebb.ARR_VERTEX_POS).astype(np.int64)
+    rank = G.export(ebb.ARR_RANK)
+    eu, ev = oracle.edge_list(g)
+    assert np.array_equal(np.sort(rank), np.arange(g.m))
+    lo, hi = np.minimum(pos[eu], pos[ev]), np.maximum(pos[eu], pos[ev])
+    key = lo * g.n + hi
+    assert (np.diff(key[np.argsort(rank)]) > 0).all()  # lexicographic in (first, second) position
+    assert np.array_equal(G.export(ebb.ARR_SUBSIZE), oracle.seed_sizes(g, rank))
+    rng = np.random.default_rng(ordering)
+    eids = rng.choice(g.m, size=min(g.m, 400), replace=False).astype(np.int64)
+    for k in (3, 4, 5, 6, 7):
+        out = np.zeros(len(eids), np.uint64)
+        ebb.ebbkc_count_seeds(G.handle, k, eids, out)
+        assert np.array_equal(out, oracle.seed_counts(g, rank, k, eids)), k
+    G.close()
+
+
+@pytest.mark.parametrize("name", ["er2000", "er_planted", "cocktail", "rmat10"])
+def test_counts_equal_under_every_ordering(ebb, name):
+    g = GRAPHS[name]()
+    ref = prepared(ebb, g, ebb.ORDER_HYBRID)
+    kmax = ref.max_clique_size()
+    want = {k: oracle.count(g, k) for k in range(1, kmax + 2)}
+    for ordering in (ebb.ORDER_COLOR, ebb.ORDER_DEGEN_VERTEX):
+        for kw in ({}, {"rule2": 0}, {"early_termination": 0}):
+            G = prepared(ebb, g, ordering, **kw)
+            for k in range(1, kmax + 2):
+                print(f"case ordering={ordering} {name} {kw} k={k}", flush=True)
+                assert G.count(k) == want[k], (ordering, kw, k)
+            G.close()
+    for k in range(1, kmax + 2):
+        assert ref.count(k) == want[k]
+    ref.close()
+
+
+def test_listing_under_the_colour_order(ebb):
+    import torch
+    g = configs.er_small()
+    G = prepared(ebb, g, ebb.ORDER_COLOR)
+    for k in (3, 4, 5):
+        c, ho, hu, _ = oracle.list_lex(g, k, want_tuples=False)
+        buf = torch.empty((max(c, 1), k), dtype=torch.int32, device="cuda")
+        w, go, gu = ebb.ebbkc_list(G.handle, k, buf, max(c, 1))
+        assert (w, go, gu) == (c, ho, hu), k
+    G.close()
+
+
+def test_colour_order_beyond_the_widest_class_is_refused(ebb):
+    # R-MAT scale 13: under the colour order one sub-branch holds 287 vertices (more than the 256 of
+    # the widest bitmap class; the oracle's sizes under the exported ranking say so), while the
+    # default and degeneracy orders keep every sub-branch within it
+    g = configs.rmat_scale(13)
+    G = prepared(ebb, g, ebb.ORDER_COLOR)
+    sizes = oracle.seed_sizes(g, G.export(ebb.ARR_RANK))
+    assert sizes.max() > 256
+    with pytest.raises(ebb.EbbkcError) as ei:
+        G.count(5)
+    assert ei.value.status == ebb.E_WIDTH
+    G.close()
+    want = oracle.count(g, 5)
+    for ordering in (ebb.ORDER_HYBRID, ebb.ORDER_DEGEN_VERTEX):
+        G = prepared(ebb, g, ordering)
+        assert G.export(ebb.ARR_SUBSIZE).max() <= 256
+        assert G.count(5) == want
+        G.close()
