@@ -95,11 +95,17 @@ typedef struct {
                                     positions, each g_i coloured on its own: vertex-oriented
                                     branching (Algorithm VBBkC, degeneracy order) with its first
                                     two steps taken together, the edge-parallel scheme of
-                                    Section 6.2 (7).  Other values: EBBKC_E_INVALID_ARG. */
+                                    Section 6.2 (7);
+                                  EBBKC_ORDER_TRUSS (3): the truss-based order at every level
+                                    (EBBkC-T, Section 4.2): size pruning and the clique / 2-plex
+                                    terminations, no colour rules; k <= 99.  It applies to the
+                                    counting calls; listings and batches under it use the
+                                    colour order below the initial branch (same result).
+                                  Other values: EBBKC_E_INVALID_ARG. */
     int32_t reserved[5];
 } ebbkc_options;
 
-enum { EBBKC_ORDER_HYBRID = 0, EBBKC_ORDER_COLOR = 1, EBBKC_ORDER_DEGEN_VERTEX = 2 };
+enum { EBBKC_ORDER_HYBRID = 0, EBBKC_ORDER_COLOR = 1, EBBKC_ORDER_DEGEN_VERTEX = 2, EBBKC_ORDER_TRUSS = 3 };
 
 typedef struct {
     int32_t n;          /* vertices */

@@ -128,7 +128,32 @@ struct SearchArgs {
     unsigned long long* graph_total;
 };
 
+// EBBkC-T search (one launch per width class): the fields mean what they mean
+// in SearchArgs; rp / ci / erank are the graph's CSR with edge ranks, rho a
+// slab of truss_slab_bytes(cus) bytes (a c x c rank matrix per wave)
+constexpr int TRUSS_FRAMES = 48;        // branching depth: k <= 2 * TRUSS_FRAMES + 3
+constexpr int TRUSS_BLOCKS_PER_CU = 4;   // three fit at W = 4 (LDS); a fourth finds the queue empty
+struct TrussArgs {
+    ArenaView A;
+    const int64_t* tasks;
+    int64_t ntasks;
+    int32_t k;
+    int32_t opts;
+    int32_t tplex;
+    const int32_t* rp;
+    const int32_t* ci;
+    const int32_t* erank;
+    int32_t* rho;
+    unsigned long long* next;
+    unsigned long long* total;
+    unsigned long long* work;
+    int* err;
+    uint64_t* per_task;
+};
+
 hipError_t launch_build(int W, const BuildArgs& a, int cus, hipStream_t s);
+hipError_t launch_search_truss(int W, const TrussArgs& a, int cus, hipStream_t s);
+size_t truss_slab_bytes(int cus);
 hipError_t launch_search(int W, bool list, const SearchArgs& a, int cus, int blocks_per_cu, hipStream_t s);
 int64_t search_grid_waves(int W, bool list, int64_t ntasks, int cus, int blocks_per_cu);
 size_t search_frame_bytes(int W);

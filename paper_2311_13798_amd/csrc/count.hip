@@ -395,6 +395,18 @@ static size_t task_bytes(int64_t n, int64_t T) {
 static ebbkc_status run_tasks(ebbkc_graph* g, int32_t k, const int64_t* tsorted, const uint64_t ccount[4],
                               uint64_t* per_task, const uint64_t* task_off, int32_t* out, void* gframes, bool list,
                               hipStream_t s) {
+    const bool truss = !list && g->opt.ordering == EBBKC_ORDER_TRUSS;
+    if (truss) {  // EBBkC-T: depth limit and the per-wave rank matrices
+        if (k > 2 * TRUSS_FRAMES + 3) return EBBKC_E_K_RANGE;
+        if (!g->rho_slab) {
+            hipError_t e = hipMalloc((void**)&g->rho_slab, truss_slab_bytes(g->cu_count));
+            if (e != hipSuccess) {
+                (void)hipGetLastError();
+                g->rho_slab = nullptr;
+                return e == hipErrorOutOfMemory ? EBBKC_E_OOM : EBBKC_E_HIP;
+            }
+        }
+    }
     hipEvent_t ev[MAX_W + 1][2] = {};
     int64_t off = 0;
     for (int W = 1; W <= MAX_W; ++W) {
@@ -423,8 +435,29 @@ static ebbkc_status run_tasks(ebbkc_graph* g, int32_t k, const int64_t* tsorted,
         a.gframes = gframes;
         CHKH(hipMemsetAsync(a.next, 0, sizeof(uint64_t), s));
         CHKH(hipEventRecord(ev[W][0], s));
-        if (list) CHKH(launch_list(W, a, g->cu_count, s));
-        else CHKH(launch_search(W, false, a, g->cu_count, g->opt.blocks_per_cu, s));
+        if (list) {
+            CHKH(launch_list(W, a, g->cu_count, s));
+        } else if (truss) {
+            TrussArgs t{};
+            t.A = a.A;
+            t.tasks = a.tasks;
+            t.ntasks = a.ntasks;
+            t.k = k;
+            t.opts = a.opts;
+            t.tplex = g->opt.t_plex;
+            t.rp = g->rp;
+            t.ci = g->ci;
+            t.erank = g->erank;
+            t.rho = g->rho_slab;
+            t.next = a.next;
+            t.total = a.total;
+            t.work = a.work;
+            t.err = a.err;
+            t.per_task = a.per_task;
+            CHKH(launch_search_truss(W, t, g->cu_count, s));
+        } else {
+            CHKH(launch_search(W, false, a, g->cu_count, g->opt.blocks_per_cu, s));
+        }
         CHKH(hipEventRecord(ev[W][1], s));
         off += nt;
     }

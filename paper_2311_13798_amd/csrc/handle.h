@@ -58,6 +58,7 @@ struct ebbkc_graph {
 
     // per-call scratch (grown on demand, freed by destroy)
     void* scratch = nullptr;
+    int32_t* rho_slab = nullptr;      // edge-rank matrices of the EBBkC-T search (allocated on first use)
     size_t scratch_bytes = 0;
     uint64_t* d_counters = nullptr;   // small device counters
     uint64_t* h_counters = nullptr;   // pinned mirror

@@ -985,6 +985,221 @@ __global__ __launch_bounds__(256, (W <= 3 ? 3 : 2)) void k_search(SearchArgs a) 
     }
 }
 
+// ---------------------------------------------------------------- EBBkC-T
+// Algorithm EBBkC-T: the truss-based order pi_tau at every level.  A node is
+// (P, r): vertices P of the seed's g_i and the edges among them ranked after
+// r in pi_tau (r = rank of the edge added last; every edge of g_i is ranked
+// after its seed, so the root is (V(g_i), -1)).  The children are the node's
+// edges f = (x, y), each with the vertices of P joined to both x and y by
+// edges ranked after f (Eq. edge-oriented-branching under pi_tau restricted
+// to the node).  Size pruning and the clique / 2-plex terminations apply;
+// the colour rules do not (the order is not colour-based).  A task keeps the
+// ranks of g_i's edges in a c x c matrix in its wave's slab of device memory;
+// lane j writes and reads only columns j mod 64, so no lane reads another's
+// stores.  Root tasks [x0, x1) take the root edges (x, y), x < y, x in range.
+
+template <int W>
+struct TFrame {
+    uint64_t P[W];
+    uint64_t Y[W];  // y still to visit with the current x
+    int32_t r, l, x, pad;
+};
+
+template <int W>
+struct TMem {
+    uint64_t rows[64 * W][W];
+    TFrame<W> fr[TRUSS_FRAMES];
+};
+
+template <int W>
+__global__ __launch_bounds__(256, 2) void k_search_truss(TrussArgs a) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    TMem<W>& M = reinterpret_cast<TMem<W>*>(smem_raw)[threadIdx.x / 64];
+    constexpr int C = 64 * W;
+    int32_t* rho = a.rho + ((int64_t)blockIdx.x * 4 + threadIdx.x / 64) * (int64_t)C * C;
+    const int lane = lane_id();
+    const bool et = a.opts & OPT_ET, work = a.opts & OPT_WORK;
+    const bool t2 = et && a.tplex != 1;
+    Acc acc{0, false};
+    uint64_t wk_tasks = 0, wk_nodes = 0, wk_ops = 0;
+
+    for (;;) {
+        unsigned long long it = 0;
+        if (lane == 0) it = atomicAdd(a.next, 1ull);
+        it = uni64(__shfl(it, 0, 64));
+        if ((int64_t)it >= a.ntasks) break;
+        const int64_t task = a.tasks[it];
+        const int64_t slot = task_slot(task);
+        const ArenaView& A = a.A;
+        const int c = uniform_i32(A.seed_c[slot]);
+        const int l0 = a.k - 2;
+        // root ranges cover the first clique vertices 0..c-l0; here x is the
+        // lower end of a clique's first edge in pi_tau, which may lie past
+        // them, so the last range runs to c
+        const int x0 = task_x0(task), x1 = task_x1(task) >= c - l0 + 1 ? c : task_x1(task);
+        const int64_t ro = A.row_off[slot], vo = A.vtx_off[slot];
+        Acc tacc{0, false};
+        wk_tasks += work;
+        for (int i = lane; i < c * W; i += 64) (&M.rows[0][0])[i] = A.rows[ro + i];
+        wave_sync();
+        // ranks of g_i's edges (entries of non-adjacent pairs are never read)
+        for (int i = 0; i < c; ++i) {
+            const int32_t gu = A.gid[vo + i];
+            const int b = a.rp[gu], e = a.rp[gu + 1];
+#pragma unroll
+            for (int q = 0; q < W; ++q) {
+                const int j = lane + 64 * q;
+                if (j < c && ((M.rows[i][q] >> lane) & 1)) {
+                    const int p = lower_bound_i32(a.ci, b, e, A.gid[vo + j]);
+                    rho[i * C + j] = a.erank[p];
+                }
+            }
+        }
+        if (work) wk_ops += (uint64_t)c * W;
+
+        // nodes that need no branching: counts them (true) or returns false
+        auto eval = [&](const uint64_t (&P)[W], int r, int l, u128& val) -> bool {
+            const int pc = popcW(P);
+            val = 0;
+            if (work) wk_nodes += 1;
+            if (pc < l) return true;
+            if (l == 1) { val = (uint64_t)pc; return true; }
+            int mn = 1 << 30, nf = 0;
+            uint32_t dsum = 0;
+#pragma unroll
+            for (int q = 0; q < W; ++q) {
+                const int w = lane + 64 * q;
+                if ((P[q] >> lane) & 1) {
+                    int d = 0;
+#pragma unroll
+                    for (int ww = 0; ww < W; ++ww) {
+                        uint64_t bits = P[ww] & M.rows[w][ww];
+                        while (bits) {
+                            const int u = 64 * ww + __builtin_ctzll(bits);
+                            bits &= bits - 1;
+                            d += rho[u * C + w] > r;
+                        }
+                    }
+                    mn = d < mn ? d : mn;
+                    nf += d == pc - 1;
+                    dsum += d;
+                }
+            }
+            if (work) wk_ops += (uint64_t)pc * W;
+            const uint64_t twoE = wsum_u32(dsum);
+            if (l == 2) { val = twoE / 2; return true; }
+            if (et) {
+                const int mind = wmin_i32(mn);
+                if (mind >= pc - 1) { val = binom128(pc, l, tacc.ovf); return true; }
+                if (t2 && mind >= pc - 2) {
+                    const int nfull = (int)wsum_u32((uint32_t)nf);
+                    val = twoplex_count(nfull, (pc - nfull) / 2, l, tacc.ovf);
+                    return true;
+                }
+            }
+            return false;
+        };
+        auto write_frame = [&](int d, const uint64_t (&P)[W], int r, int l) {
+            TFrame<W>& F = M.fr[d];
+#pragma unroll
+            for (int w = 0; w < W; ++w) { F.P[w] = P[w]; F.Y[w] = 0; }
+            F.r = r;
+            F.l = l;
+            F.x = -1;
+            wave_sync();
+        };
+
+        uint64_t P0[W];
+        prefix_mask(c, P0);
+        bool done = false;
+        if (x0 == 0 && x1 == c) {
+            u128 v = 0;
+            if (eval(P0, -1, l0, v)) { tacc.add(v); done = true; }
+        }
+        int sp = 0;
+        if (!done) write_frame(0, P0, -1, l0);
+        while (!done && sp >= 0) {
+            TFrame<W>& F = M.fr[sp];
+            uint64_t P[W], Y[W];
+#pragma unroll
+            for (int w = 0; w < W; ++w) { P[w] = uni64(F.P[w]); Y[w] = uni64(F.Y[w]); }
+            const int r = uniform_i32(F.r), l = uniform_i32(F.l);
+            int x = uniform_i32(F.x);
+            int y = -1;
+#pragma unroll
+            for (int w = W - 1; w >= 0; --w)
+                if (Y[w]) y = 64 * w + __builtin_ctzll(Y[w]);
+            if (y < 0) {  // next x of the node, and its children's y
+                int nx = -1;
+#pragma unroll
+                for (int w = W - 1; w >= 0; --w) {
+                    const uint64_t b = P[w] & upper_mask(x, w);
+                    if (b) nx = 64 * w + __builtin_ctzll(b);
+                }
+                if (nx < 0 || (sp == 0 && (nx < x0 || nx >= x1))) {
+                    if (sp == 0 && nx >= 0 && nx < x0) {  // the root starts at x0
+                        F.x = x0 - 1;
+                        wave_sync();
+                        continue;
+                    }
+                    --sp;
+                    continue;
+                }
+#pragma unroll
+                for (int q = 0; q < W; ++q) {
+                    const int j = lane + 64 * q;
+                    bool ok = ((P[q] & M.rows[nx][q] & upper_mask(nx, q)) >> lane) & 1;
+                    if (ok) ok = rho[nx * C + j] > r;
+                    F.Y[q] = uni64(ballot(ok));
+                }
+                F.x = nx;
+                wave_sync();
+                if (work) wk_ops += W;
+                continue;
+            }
+            if (lane == 0) F.Y[y >> 6] = Y[y >> 6] & (Y[y >> 6] - 1);
+            wave_sync();
+            // child of edge (x, y): P joined to x and y by edges ranked after it
+            int rv = 0;
+            if (lane == (y & 63)) rv = rho[x * C + y];
+            const int rf = __shfl(rv, y & 63, 64);
+            uint64_t Pc[W];
+#pragma unroll
+            for (int q = 0; q < W; ++q) {
+                const int j = lane + 64 * q;
+                bool in = ((P[q] & M.rows[x][q] & M.rows[y][q]) >> lane) & 1;
+                if (in) in = rho[x * C + j] > rf && rho[y * C + j] > rf;
+                Pc[q] = uni64(ballot(in));
+            }
+            if (work) wk_ops += W;
+            const int lc = l - 2;
+            u128 v = 0;
+            if (eval(Pc, rf, lc, v)) { tacc.add(v); continue; }
+            if (sp + 1 >= TRUSS_FRAMES) {
+                if (lane == 0) atomicOr(a.err, ERR_DEPTH);
+                break;
+            }
+            ++sp;
+            write_frame(sp, Pc, rf, lc);
+        }
+        if (tacc.ovf && lane == 0) atomicOr(a.err, ERR_OVERFLOW);
+        if (a.per_task && lane == 0) a.per_task[it] = tacc.lo();
+        acc.add(tacc.v);
+        wave_sync();
+    }
+    if (work && lane == 0) {
+        atomicAdd(&a.work[0], (unsigned long long)wk_tasks);
+        atomicAdd(&a.work[1], (unsigned long long)wk_nodes);
+        atomicAdd(&a.work[2], (unsigned long long)wk_ops);
+    }
+    if (acc.ovf && lane == 0) atomicOr(a.err, ERR_OVERFLOW);
+    if (lane == 0 && acc.v) {
+        const unsigned long long old = atomicAdd(&a.total[0], (unsigned long long)acc.lo());
+        const unsigned long long carry = (old + acc.lo() < old) ? 1ull : 0ull;
+        if (acc.hi() + carry) atomicAdd(&a.total[1], (unsigned long long)(acc.hi() + carry));
+    }
+}
+
 namespace {
 
 template <int W, bool LIST>
@@ -1052,6 +1267,36 @@ size_t search_frame_bytes(int W) {
         case 4: return sizeof(Frame<4>);
     }
     return 0;
+}
+
+namespace {
+template <int W>
+hipError_t launch_truss_w(const TrussArgs& a, int cus, hipStream_t s) {
+    auto kern = k_search_truss<W>;
+    const size_t smem = 4 * sizeof(TMem<W>);
+    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+    if (e != hipSuccess) return e;
+    int64_t grid = (int64_t)cus * TRUSS_BLOCKS_PER_CU, need = (a.ntasks + 3) / 4;
+    if (grid > need) grid = need;
+    if (grid < 1) grid = 1;
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(256), smem, s, a);
+    return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_search_truss(int W, const TrussArgs& a, int cus, hipStream_t s) {
+    if (a.ntasks <= 0) return hipSuccess;
+    switch (W) {
+        case 1: return launch_truss_w<1>(a, cus, s);
+        case 2: return launch_truss_w<2>(a, cus, s);
+        case 3: return launch_truss_w<3>(a, cus, s);
+        case 4: return launch_truss_w<4>(a, cus, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+size_t truss_slab_bytes(int cus) {
+    return (size_t)cus * TRUSS_BLOCKS_PER_CU * 4 * (size_t)(64 * MAX_W) * (64 * MAX_W) * sizeof(int32_t);
 }
 
 float k4_weight_of(int32_t dense_k4) { return dense_k4 < 0 ? 0.f : (dense_k4 == 0 ? 1.f : 0.01f * (float)dense_k4); }

@@ -1,7 +1,8 @@
 """Initial-branch edge orders of the ablation orderings: EBBkC-C (Section 4.3: one greedy colouring
 of G, vertices by non-increasing colour, edges in the lexicographic order of their endpoints'
 positions, G's colours kept in every sub-branch) and the edge-parallel VBBkC root (Algorithm VBBkC in
-a degeneracy order with its first two branching steps taken together, Section 6.2 (7)).
+a degeneracy order with its first two branching steps taken together, Section 6.2 (7)), and EBBkC-T
+(Algorithm EBBkC-T: pi_tau at every level).
 
 The vertex orders are checked against their definitions written out here (sequential greedy
 colouring, level-synchronous core peel), the edge ranks against the lexicographic rule, sub-branch
@@ -135,10 +136,14 @@ def test_counts_equal_under_every_ordering(ebb, name):
     ref = prepared(ebb, g, ebb.ORDER_HYBRID)
     kmax = ref.max_clique_size()
     want = {k: oracle.count(g, k) for k in range(1, kmax + 2)}
-    for ordering in (ebb.ORDER_COLOR, ebb.ORDER_DEGEN_VERTEX):
+    for ordering in (ebb.ORDER_COLOR, ebb.ORDER_DEGEN_VERTEX, ebb.ORDER_TRUSS):
         for kw in ({}, {"rule2": 0}, {"early_termination": 0}):
+            if ordering == ebb.ORDER_TRUSS and "rule2" in kw:
+                continue  # no colour rules under EBBkC-T
             G = prepared(ebb, g, ordering, **kw)
             for k in range(1, kmax + 2):
+                if ordering == ebb.ORDER_TRUSS and kw and k > 10:
+                    break  # EBBkC-T without terminations branches through every planted clique
                 print(f"case ordering={ordering} {name} {kw} k={k}", flush=True)
                 assert G.count(k) == want[k], (ordering, kw, k)
             G.close()
@@ -177,3 +182,35 @@ def test_colour_order_beyond_the_widest_class_is_refused(ebb):
         assert G.export(ebb.ARR_SUBSIZE).max() <= 256
         assert G.count(5) == want
         G.close()
+
+
+@pytest.mark.parametrize("name", ["er_planted", "rmat10"])
+def test_truss_order_per_seed_counts(ebb, name):
+    # per-seed counts do not depend on the order inside a sub-branch: under EBBkC-T they equal the
+    # oracle's for the truss ranking, with and without the terminations, and with split roots
+    g = GRAPHS[name]()
+    tr = oracle.truss_levelsync(g)
+    rng = np.random.default_rng(3)
+    eids = rng.choice(g.m, size=min(g.m, 400), replace=False).astype(np.int64)
+    for kw in ({}, {"early_termination": 0}, {"split_threshold": 64}):
+        G = prepared(ebb, g, ebb.ORDER_TRUSS, **kw)
+        assert np.array_equal(G.export(ebb.ARR_RANK), tr["rank"])
+        for k in (5, 6, 7, 9):
+            out = np.zeros(len(eids), np.uint64)
+            ebb.ebbkc_count_seeds(G.handle, k, eids, out)
+            assert np.array_equal(out, oracle.seed_counts(g, tr["rank"], k, eids)), (kw, k)
+        G.close()
+
+
+def test_truss_order_depth_limit(ebb):
+    # K_120: tau = 118; EBBkC-T branches at most 48 levels deep, so k <= 99, checked up front (here
+    # every sub-branch and every child of a split root is a clique and terminates at once)
+    from math import comb
+    g = graphgen.complete(120)
+    G = prepared(ebb, g, ebb.ORDER_TRUSS)
+    for k in (5, 40, 99):
+        assert G.count128(k) == comb(120, k)
+    with pytest.raises(ebb.EbbkcError) as ei:
+        G.count(100)
+    assert ei.value.status == ebb.E_K_RANGE
+    G.close()
