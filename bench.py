@@ -22,6 +22,8 @@ Also reported on the same JSON line:
                 chunk into one 80 GB device buffer: tuples/s and GB/s written (HBM-write bound).
   batched       many small graphs with per-graph k: one launch per (graph, k) vs the fused
                 batch (one persistent launch per width class, replayed from a HIP graph).
+  ablation      (--ablation) the same engine under the paper's variants: orderings C, T and the
+                edge-parallel VBBkC root, Rule (2) off, early termination off, t = 1 / 3.
   served        Poisson request streams (50, 200, 1000 requests/s) over a mixed resident catalogue
                 against the native continuous-batching server: p50/p99 latency from arrival to
                 result, k-cliques per second, every result equal to the same request run alone.
@@ -29,7 +31,6 @@ Also reported on the same JSON line:
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -47,21 +48,14 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def search_source_hash():
-    h = hashlib.sha256()
-    for f in ("search.hip", "arena.h", "device_util.h", "common.h"):
-        with open(os.path.join(ROOT, "paper_2311_13798_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()
-
-
 def traffic_for(kernel: str, k: int):
     """HBM bytes per launch of the given kernel at k, from the committed counter record, if it
     was taken on the current kernel source."""
     if not os.path.exists(TRAFFIC_RECORD):
         return None
     rec = json.load(open(TRAFFIC_RECORD))
-    if rec.get("source_sha256") != search_source_hash():
+    from paper_2311_13798_amd.traffic_probe import source_sha256
+    if rec.get("source_sha256") != source_sha256():
         return None
     e = rec.get("launches", {}).get(f"{kernel}@k={k}")
     return None if e is None else e.get("hbm_bytes")
@@ -153,6 +147,45 @@ def systems_forms(ebb, np, torch, configs):
     return batched, served
 
 
+def ablation(ebb, torch, configs, graphgen):
+    """Variants of the path on the same engine (Section 6.2 (3)-(5), (7)): orderings H (default), C, T
+    and the edge-parallel VBBkC root, Rule (2) off, early termination off, t fixed to 1, 2, 3.  Times
+    are wall-clock per count on the prepared graph (arena built beforehand); a variant stops at the
+    first k over 10 s, and a refused count (sub-branch wider than 256) is reported as such."""
+    variants = [("H", {}), ("H-no-rule2", {"rule2": 0}), ("H-no-ET", {"early_termination": 0}),
+                ("H-t1", {"t_plex": 1}), ("H-t3", {"t_plex": 3}), ("C", {"ordering": 1}),
+                ("VBBkC-EP", {"ordering": 2, "rule2": 0}), ("T", {"ordering": 3})]
+    graphs = [("R-MAT s12", lambda: graphgen.rmat(12, 16, seed=1), (6, 7, 8, 9, 10)),
+              ("Chung-Lu 1e6 + planted", configs.cl_planted, (8, 10, 12)),
+              ("R-MAT s18", configs.rmat18, (5, 6, 7))]
+    out = {}
+    for gname, mk, gks in graphs:
+        g = mk()
+        out[gname] = {}
+        for vname, kw in variants:
+            o = ebb.ebbkc_default_options()
+            for key, v in kw.items():
+                setattr(o, key, v)
+            G = ebb.Graph.from_csr(g, options=o)
+            rec = {}
+            try:
+                G.count(4)
+                for k in gks:
+                    t = time.perf_counter()
+                    G.count(k)
+                    dt = time.perf_counter() - t
+                    rec[str(k)] = round(dt * 1e3, 2)
+                    log(f"ablation {gname} {vname} k={k} {dt * 1e3:.1f} ms")
+                    if dt > 10.0:
+                        break
+            except ebb.EbbkcError as e:
+                rec["refused"] = str(e)
+                log(f"ablation {gname} {vname} refused: {e}")
+            G.close()
+            out[gname][vname] = rec
+    return {"unit": "ms per count", "variants": {v: kw for v, kw in variants}, "results": out}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -163,6 +196,7 @@ def main():
     ap.add_argument("--no-systems", action="store_true", help="skip the batched and served forms")
     ap.add_argument("--no-list", action="store_true", help="skip the full k = 5 listing")
     ap.add_argument("--cpu-threads", type=int, default=0)
+    ap.add_argument("--ablation", action="store_true", help="also time the ordering / rule / termination variants")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU sharding of this "
@@ -249,6 +283,10 @@ def main():
 
     if not args.no_systems:
         line["batched"], line["served"] = systems_forms(ebb, np, torch, configs)
+
+    if args.ablation:
+        import graphgen
+        line["ablation"] = ablation(ebb, torch, configs, graphgen)
 
     if not args.no_cpu_baseline:
         import oracle
