@@ -74,3 +74,31 @@ def test_full_k5_listing_in_chunks(setup):
     assert total == ref["count"] == fx["counts"]["5"]
     assert str(hu) == ref["unordered"]
     assert nch > 1
+
+
+@pytest.mark.parametrize("ordering,ks", [(2, (3, 4, 5, 6, 7)), (3, (5,))])
+def test_counts_under_other_orderings(setup, ordering, ks):
+    # the edge-parallel VBBkC root (degeneracy order) and EBBkC-T at full size: the stored oracle
+    # counts; under the degeneracy order every sub-branch stays within 256 vertices (the test's own
+    # check of the exported sizes), under EBBkC-T the arena is the default one
+    ebb, fx, g, _ = setup
+    o = ebb.ebbkc_default_options()
+    o.ordering = ordering
+    G = ebb.Graph.from_csr(g, options=o)
+    assert G.export(ebb.ARR_SUBSIZE).max() <= 256
+    for k in ks:
+        print(f"case rmat18 ordering={ordering} k={k}", flush=True)
+        assert G.count(k) == fx["counts"][str(k)], k
+    G.close()
+
+
+def test_counts_with_three_plex_terminations(setup):
+    # t = 3 forced on (the rule picks t = 2 here since 2k <= tau = 163): the stored oracle counts
+    ebb, fx, g, _ = setup
+    o = ebb.ebbkc_default_options()
+    o.t_plex = 3
+    G = ebb.Graph.from_csr(g, options=o)
+    for k in (5, 6, 7):
+        print(f"case rmat18 t3 k={k}", flush=True)
+        assert G.count(k) == fx["counts"][str(k)], k
+    G.close()
