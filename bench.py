@@ -23,7 +23,7 @@ Also reported on the same JSON line:
   batched       many small graphs with per-graph k: one launch per (graph, k) vs the fused
                 batch (one persistent launch per width class, replayed from a HIP graph).
   ablation      (--ablation) the same engine under the paper's variants: orderings C, T and the
-                edge-parallel VBBkC root, Rule (2) off, early termination off, t = 1 / 3.
+                edge- and node-parallel VBBkC roots, Rule (2) off, early termination off, t = 1 / 3.
   served        Poisson request streams (50, 200, 1000 requests/s) over a mixed resident catalogue
                 against the native continuous-batching server: p50/p99 latency from arrival to
                 result, k-cliques per second, every result equal to the same request run alone.
@@ -149,12 +149,13 @@ def systems_forms(ebb, np, torch, configs):
 
 def ablation(ebb, torch, configs, graphgen):
     """Variants of the path on the same engine (Section 6.2 (3)-(5), (7)): orderings H (default), C, T
-    and the edge-parallel VBBkC root, Rule (2) off, early termination off, t fixed to 1, 2, 3.  Times
+    and the edge- and node-parallel VBBkC roots, Rule (2) off, early termination off, t fixed to 1, 3.  Times
     are wall-clock per count on the prepared graph (arena built beforehand); a variant stops at the
     first k over 10 s, and a refused count (sub-branch wider than 256) is reported as such."""
     variants = [("H", {}), ("H-no-rule2", {"rule2": 0}), ("H-no-ET", {"early_termination": 0}),
                 ("H-t1", {"t_plex": 1}), ("H-t3", {"t_plex": 3}), ("C", {"ordering": 1}),
-                ("VBBkC-EP", {"ordering": 2, "rule2": 0}), ("T", {"ordering": 3})]
+                ("VBBkC-EP", {"ordering": 2, "rule2": 0}), ("VBBkC-NP", {"ordering": 4, "rule2": 0}),
+                ("T", {"ordering": 3})]
     graphs = [("R-MAT s12", lambda: graphgen.rmat(12, 16, seed=1), (6, 7, 8, 9, 10)),
               ("Chung-Lu 1e6 + planted", configs.cl_planted, (8, 10, 12)),
               ("R-MAT s18", configs.rmat18, (5, 6, 7))]

@@ -101,11 +101,23 @@ typedef struct {
                                     terminations, no colour rules; k <= 99.  It applies to the
                                     counting calls; listings and batches under it use the
                                     colour order below the initial branch (same result).
+                                  EBBKC_ORDER_DEGEN_VERTEX_NP (4): the same vertex order and
+                                    edge ranks as DEGEN_VERTEX, but a whole-graph count takes one
+                                    root per vertex v, G[N+(v)] (the node-parallel scheme of
+                                    Section 6.2 (7)); |N+(v)| <= 256 or EBBKC_E_WIDTH.  Rank ranges,
+                                    per-seed counts, listings and batches under it use the edge
+                                    roots of DEGEN_VERTEX (same results).
                                   Other values: EBBKC_E_INVALID_ARG. */
     int32_t reserved[5];
 } ebbkc_options;
 
-enum { EBBKC_ORDER_HYBRID = 0, EBBKC_ORDER_COLOR = 1, EBBKC_ORDER_DEGEN_VERTEX = 2, EBBKC_ORDER_TRUSS = 3 };
+enum {
+    EBBKC_ORDER_HYBRID = 0,
+    EBBKC_ORDER_COLOR = 1,
+    EBBKC_ORDER_DEGEN_VERTEX = 2,
+    EBBKC_ORDER_TRUSS = 3,
+    EBBKC_ORDER_DEGEN_VERTEX_NP = 4
+};
 
 typedef struct {
     int32_t n;          /* vertices */
@@ -129,7 +141,8 @@ enum {
     EBBKC_ARR_LEVEL = 2,   /* int32[m]: truss level of each edge */
     EBBKC_ARR_SUBSIZE = 3, /* int32[m]: |V(g_i)| of each edge's sub-branch */
     EBBKC_ARR_VERTEX_POS = 4,   /* int32[n]: position of each vertex in the vertex order the
-                                   edge ranks follow (orderings COLOR and DEGEN_VERTEX only) */
+                                   edge ranks follow (orderings COLOR, DEGEN_VERTEX and
+                                   DEGEN_VERTEX_NP only) */
     EBBKC_ARR_VERTEX_COLOR = 5  /* int32[n]: colour (1, 2, ...) of each vertex in the greedy
                                    colouring of G (ordering COLOR only) */
 };

@@ -21,7 +21,7 @@ OK, E_INVALID_ARG, E_BAD_CSR, E_OOM, E_K_RANGE, E_BUFFER_TOO_SMALL, E_OVERFLOW, 
 PTR_HOST, PTR_DEVICE = 0, 1
 LIST_SORTED = 1
 ARR_SUPPORT, ARR_RANK, ARR_LEVEL, ARR_SUBSIZE, ARR_VERTEX_POS, ARR_VERTEX_COLOR = 0, 1, 2, 3, 4, 5
-ORDER_HYBRID, ORDER_COLOR, ORDER_DEGEN_VERTEX, ORDER_TRUSS = 0, 1, 2, 3
+ORDER_HYBRID, ORDER_COLOR, ORDER_DEGEN_VERTEX, ORDER_TRUSS, ORDER_DEGEN_VERTEX_NP = 0, 1, 2, 3, 4
 
 
 class EbbkcError(RuntimeError):

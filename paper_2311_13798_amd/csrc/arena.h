@@ -53,6 +53,8 @@ struct BuildArgs {
     int16_t* col;
     uint64_t* nedges;  // edges of g_i per slot
     const int32_t* vcol;  // colours of G kept in every g_i, or null: each g_i coloured on its own
+    const int32_t* seed_rthr;  // vertex slots: seed_eid holds the vertex, its sub-branch is its
+                               // neighbourhood through edges ranked after seed_rthr; null: edge slots
     unsigned long long* next;
     int* err;
 };

@@ -89,6 +89,47 @@ __global__ void k_seed_fill(const int32_t* __restrict__ byrank, const int32_t* _
     }
 }
 
+// node-parallel roots: |N+(v)| (neighbours later in the vertex order) per vertex
+__global__ void k_vertex_out(const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                             const int32_t* __restrict__ vpos, int32_t n, int32_t* __restrict__ cout,
+                             int32_t* __restrict__ byvpos) {
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t pv = vpos[v];
+        int32_t c = 0;
+        for (int32_t j = rp[v]; j < rp[v + 1]; ++j) c += vpos[ci[j]] > pv;
+        cout[pv] = c;  // indexed by position
+        byvpos[pv] = (int32_t)v;
+    }
+}
+
+__global__ void k_vertex_flags(const int32_t* __restrict__ cout, int32_t n, int32_t* __restrict__ flag) {
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x)
+        flag[p] = cout[p] >= 1;
+}
+
+// slot of the vertex at position p: its out-edges are the ranks [R, R + c) (edges are ranked
+// lexicographically by their endpoints' positions), so its sub-branch is the neighbourhood through
+// edges ranked after R - 1
+__global__ void k_vertex_fill(const int32_t* __restrict__ cout, const int32_t* __restrict__ byvpos,
+                              const int64_t* __restrict__ rstart, const int32_t* __restrict__ flag,
+                              const int64_t* __restrict__ pos, int32_t n, int32_t* __restrict__ seed_v,
+                              int32_t* __restrict__ seed_c, int32_t* __restrict__ seed_rthr,
+                              int32_t* __restrict__ seed_rank, int64_t* __restrict__ rwords,
+                              int64_t* __restrict__ vcount, int* __restrict__ err) {
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
+        if (!flag[p]) continue;
+        const int64_t s = pos[p];
+        const int32_t c = cout[p];
+        if (c > 64 * MAX_W) atomicOr(err, ERR_WIDTH);
+        seed_v[s] = byvpos[p];
+        seed_c[s] = c;
+        seed_rthr[s] = (int32_t)(rstart[p] - 1);
+        seed_rank[s] = (int32_t)rstart[p];
+        rwords[s] = (int64_t)c * width_of(c);
+        vcount[s] = c;
+    }
+}
+
 // slots of one width class, in slot order
 __global__ void k_class_flags(const int32_t* __restrict__ seed_c, int64_t n, int W, int32_t* __restrict__ flag) {
     for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < n; s += (int64_t)gridDim.x * blockDim.x)
@@ -170,6 +211,13 @@ struct DBuf {
     T* release() { T* q = p; p = nullptr; return q; }
 };
 
+struct SlotArrays {
+    uint64_t* rows = nullptr;
+    int32_t* gid = nullptr;
+    int16_t* col = nullptr;
+    uint64_t* ned = nullptr;
+};
+
 }  // namespace
 
 hipError_t ensure_tables(int dev, hipStream_t s) { return ensure_binom(dev, s); }
@@ -211,6 +259,10 @@ ebbkc_status subsize_impl(ebbkc_graph* g, hipStream_t s) {
     g->subsize_ready = true;
     return EBBKC_OK;
 }
+
+static ebbkc_status build_slots(ebbkc_graph* g, int64_t ns, const int32_t* seid, const int32_t* sc,
+                                const int32_t* srthr, const int64_t* roff, const int64_t* voff, const int64_t tot[2],
+                                int64_t* tmp, SlotArrays& out, hipStream_t s);
 
 ebbkc_status arena_impl(ebbkc_graph* g, hipStream_t s) {
     if (g->arena_built) return EBBKC_OK;
@@ -258,6 +310,39 @@ ebbkc_status arena_impl(ebbkc_graph* g, hipStream_t s) {
     if (ns) CHKH(hipMemcpyAsync(g->seed_rank_host.data(), srank.p, sizeof(int32_t) * ns, hipMemcpyDeviceToHost, s));
     CHKH(hipStreamSynchronize(s));
     if (herr & ERR_WIDTH) return EBBKC_E_WIDTH;
+    SlotArrays out;
+    st = build_slots(g, ns, seid.p, sc.p, nullptr, roff.p, voff.p, tot, tmp.p, out, s);
+    if (st) return st;
+    CHKH(hipEventRecord(e1, s));
+    CHKH(hipStreamSynchronize(s));
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    g->arena_ms = ms;
+    g->nseeds = ns;
+    g->seed_eid = seid.release();
+    g->seed_c = sc.release();
+    g->row_off = roff.release();
+    g->vtx_off = voff.release();
+    g->arows = out.rows;
+    g->agid = out.gid;
+    g->acol = out.col;
+    g->nedges = out.ned;
+    g->arena_bytes = (int64_t)(tot[0] * 8 + tot[1] * 6 + ns * 32);
+    g->device_bytes += g->arena_bytes;
+    g->arena_built = true;
+    return EBBKC_OK;
+}
+
+// The sub-branches of ns slots -- seed edges (srthr null) or vertices with
+// the rank threshold of their out-edges -- built per width class into newly
+// allocated rows / gid / col / nedges (owned by the caller on success).
+static ebbkc_status build_slots(ebbkc_graph* g, int64_t ns, const int32_t* seid, const int32_t* sc,
+                                const int32_t* srthr, const int64_t* roff, const int64_t* voff, const int64_t tot[2],
+                                int64_t* tmp, SlotArrays& out, hipStream_t s) {
+    int* err = (int*)(g->d_counters + 6);
+    int herr = 0;
     DBuf<uint64_t> rows, ned;
     DBuf<int32_t> gid;
     DBuf<int16_t> col;
@@ -272,8 +357,8 @@ ebbkc_status arena_impl(ebbkc_graph* g, hipStream_t s) {
     CHKH(clist.alloc(ns));
     CHKH(cpos.alloc(ns + 1));
     for (int W = MAX_W; W >= 1 && ns > 0; --W) {
-        hipLaunchKernelGGL(k_class_flags, dim3(grid_for(ns)), dim3(256), 0, s, sc.p, ns, W, cflag.p);
-        CHKH(exclusive_scan_i32(cflag.p, cpos.p, ns, cpos.p + ns, tmp.p, s));
+        hipLaunchKernelGGL(k_class_flags, dim3(grid_for(ns)), dim3(256), 0, s, sc, ns, W, cflag.p);
+        CHKH(exclusive_scan_i32(cflag.p, cpos.p, ns, cpos.p + ns, tmp, s));
         hipLaunchKernelGGL(k_class_fill, dim3(grid_for(ns)), dim3(256), 0, s, cflag.p, cpos.p, ns, clist.p);
         int64_t nw = 0;
         CHKH(hipMemcpyAsync(&nw, cpos.p + ns, sizeof(int64_t), hipMemcpyDeviceToHost, s));
@@ -284,10 +369,11 @@ ebbkc_status arena_impl(ebbkc_graph* g, hipStream_t s) {
         b.G = graph_view(g);
         b.list = clist.p;
         b.n = nw;
-        b.seed_eid = seid.p;
-        b.seed_c = sc.p;
-        b.row_off = roff.p;
-        b.vtx_off = voff.p;
+        b.seed_eid = seid;
+        b.seed_c = sc;
+        b.seed_rthr = srthr;
+        b.row_off = roff;
+        b.vtx_off = voff;
         b.rows = rows.p;
         b.gid = gid.p;
         b.col = col.p;
@@ -299,27 +385,102 @@ ebbkc_status arena_impl(ebbkc_graph* g, hipStream_t s) {
         CHKH(hipStreamSynchronize(s));  // clist is reused by the next class
     }
     CHKH(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, s));
-    CHKH(hipEventRecord(e1, s));
     CHKH(hipStreamSynchronize(s));
     if (herr & ERR_WIDTH) return EBBKC_E_WIDTH;
-    float ms = 0.f;
-    (void)hipEventElapsedTime(&ms, e0, e1);
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    g->arena_ms = ms;
-    g->nseeds = ns;
-    g->seed_eid = seid.release();
-    g->seed_c = sc.release();
-    g->row_off = roff.release();
-    g->vtx_off = voff.release();
-    g->arows = rows.release();
-    g->agid = gid.release();
-    g->acol = col.release();
-    g->nedges = ned.release();
-    g->arena_bytes = (int64_t)(tot[0] * 8 + tot[1] * 6 + ns * 32);
-    g->device_bytes += g->arena_bytes;
-    g->arena_built = true;
+    out.rows = rows.release();
+    out.gid = gid.release();
+    out.col = col.release();
+    out.ned = ned.release();
     return EBBKC_OK;
+}
+
+// Node-parallel VBBkC (ordering DEGEN_VERTEX_NP): one slot per vertex v with a
+// non-empty N+(v) (neighbours later in the degeneracy order), its sub-branch
+// G[N+(v)] built by the same kernel (the neighbourhood through edges ranked
+// after v's first out-edge, all edges among it), in position order.
+static ebbkc_status vertex_arena_impl(ebbkc_graph* g, hipStream_t s) {
+    VertexArena& A = g->varena;
+    if (A.built) return EBBKC_OK;
+    ebbkc_status st = ensure_counters(g);
+    if (st) return st;
+    const int32_t n = g->n;
+    DBuf<int32_t> cout, byvpos, flag, seid, sc, srthr, srank;
+    DBuf<int64_t> rstart, pos, tmp, rwords, vcount, roff, voff;
+    CHKH(cout.alloc(n));
+    CHKH(byvpos.alloc(n));
+    CHKH(flag.alloc(n));
+    CHKH(rstart.alloc(n + 1));
+    CHKH(pos.alloc(n + 1));
+    CHKH(tmp.alloc(scan_tmp_elems(n + 1) + 64));
+    CHKH(hipMemsetAsync(g->d_counters, 0, CNT_WORDS * sizeof(uint64_t), s));
+    int* err = (int*)(g->d_counters + 6);
+    if (n) {
+        hipLaunchKernelGGL(k_vertex_out, dim3(grid_for(n)), dim3(256), 0, s, g->rp, g->ci, g->vpos, n, cout.p,
+                           byvpos.p);
+        hipLaunchKernelGGL(k_vertex_flags, dim3(grid_for(n)), dim3(256), 0, s, cout.p, n, flag.p);
+    }
+    CHKH(exclusive_scan_i32(cout.p, rstart.p, n, rstart.p + n, tmp.p, s));
+    CHKH(exclusive_scan_i32(flag.p, pos.p, n, pos.p + n, tmp.p, s));
+    int64_t ns = 0;
+    CHKH(hipMemcpyAsync(&ns, pos.p + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    CHKH(hipStreamSynchronize(s));
+    CHKH(seid.alloc(ns));
+    CHKH(sc.alloc(ns));
+    CHKH(srthr.alloc(ns));
+    CHKH(srank.alloc(ns));
+    CHKH(rwords.alloc(ns + 1));
+    CHKH(vcount.alloc(ns + 1));
+    CHKH(roff.alloc(ns + 1));
+    CHKH(voff.alloc(ns + 1));
+    if (n)
+        hipLaunchKernelGGL(k_vertex_fill, dim3(grid_for(n)), dim3(256), 0, s, cout.p, byvpos.p, rstart.p, flag.p,
+                           pos.p, n, seid.p, sc.p, srthr.p, srank.p, rwords.p, vcount.p, err);
+    CHKH(exclusive_scan_i64(rwords.p, roff.p, ns, roff.p + ns, tmp.p, s));
+    CHKH(exclusive_scan_i64(vcount.p, voff.p, ns, voff.p + ns, tmp.p, s));
+    int64_t tot[2] = {0, 0};
+    int herr = 0;
+    CHKH(hipMemcpyAsync(&tot[0], roff.p + ns, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    CHKH(hipMemcpyAsync(&tot[1], voff.p + ns, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    CHKH(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, s));
+    std::vector<int32_t> rank_host((size_t)ns);
+    if (ns) CHKH(hipMemcpyAsync(rank_host.data(), srank.p, sizeof(int32_t) * ns, hipMemcpyDeviceToHost, s));
+    CHKH(hipStreamSynchronize(s));
+    if (herr & ERR_WIDTH) return EBBKC_E_WIDTH;
+    SlotArrays out;
+    st = build_slots(g, ns, seid.p, sc.p, srthr.p, roff.p, voff.p, tot, tmp.p, out, s);
+    if (st) return st;
+    A.nseeds = ns;
+    A.seed_v = seid.release();
+    A.seed_c = sc.release();
+    A.seed_rthr = srthr.release();
+    A.row_off = roff.release();
+    A.vtx_off = voff.release();
+    A.rows = out.rows;
+    A.gid = out.gid;
+    A.col = out.col;
+    A.nedges = out.ned;
+    A.rank_host.swap(rank_host);
+    A.bytes = (int64_t)(tot[0] * 8 + tot[1] * 6 + ns * 36);
+    g->device_bytes += A.bytes;
+    A.built = true;
+    return EBBKC_OK;
+}
+
+// exchange the edge arena of the handle with its vertex arena
+static void swap_arenas(ebbkc_graph* g) {
+    VertexArena& A = g->varena;
+    std::swap(g->nseeds, A.nseeds);
+    std::swap(g->seed_eid, A.seed_v);
+    std::swap(g->seed_c, A.seed_c);
+    std::swap(g->row_off, A.row_off);
+    std::swap(g->vtx_off, A.vtx_off);
+    std::swap(g->arows, A.rows);
+    std::swap(g->agid, A.gid);
+    std::swap(g->acol, A.col);
+    std::swap(g->nedges, A.nedges);
+    std::swap(g->seed_rank_host, A.rank_host);
+    std::swap(g->arena_built, A.built);
+    g->np_active = !g->np_active;
 }
 
 static ebbkc_status read_total(ebbkc_graph* g, uint64_t* out, hipStream_t s) {
@@ -421,7 +582,8 @@ static ebbkc_status run_tasks(ebbkc_graph* g, int32_t k, const int64_t* tsorted,
         a.k = k;
         a.opts = opts_of(g->opt);
         a.k4_weight = k4_weight_of(g->opt.dense_k4);
-        a.tplex = g->opt.t_plex;
+        // under the vertex slots k is one above the clique size
+        a.tplex = g->np_active && g->opt.t_plex == 0 ? (2 * (k - 1) <= g->tau ? 2 : 3) : g->opt.t_plex;
         a.tau = g->tau;
         a.next = (unsigned long long*)(g->d_counters + W - 1);
         a.total = (unsigned long long*)(g->d_counters + 4);
@@ -478,6 +640,18 @@ ebbkc_status count_impl(ebbkc_graph* g, int32_t k, int64_t r_begin, int64_t r_en
     (void)ne;
     (void)d_per_seed;
     if (k < 3 || k > MAX_K) return EBBKC_E_K_RANGE;
+    if (g->opt.ordering == EBBKC_ORDER_DEGEN_VERTEX_NP && !g->np_active && r_begin <= 0 &&
+        (r_end < 0 || r_end >= g->m) && k + 1 <= MAX_K) {
+        // node-parallel VBBkC: one root per vertex v whose (k-1)-cliques in
+        // G[N+(v)] are counted, i.e. the edge-slot search at k + 1 over the
+        // vertex slots
+        ebbkc_status st = vertex_arena_impl(g, s);
+        if (st) return st;
+        swap_arenas(g);
+        st = count_impl(g, k + 1, 0, -1, d_eids, ne, d_per_seed, out, s);
+        swap_arenas(g);
+        return st;
+    }
     ebbkc_status st = ensure_counters(g);
     if (st) return st;
     if (ensure_binom(g->device, s) != hipSuccess) return EBBKC_E_HIP;

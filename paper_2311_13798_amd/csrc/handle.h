@@ -8,6 +8,25 @@
 
 #include "../../include/ebbkc.h"
 
+// Sub-branches of the node-parallel VBBkC roots (one slot per vertex with a
+// non-empty N+(v), in position order); swapped with the edge arena while a
+// count runs on them.
+struct VertexArena {
+    bool built = false;
+    int64_t nseeds = 0;
+    int32_t* seed_v = nullptr;     // vertex of each slot
+    int32_t* seed_c = nullptr;     // |N+(v)|
+    int32_t* seed_rthr = nullptr;  // rank of v's first out-edge minus one
+    int64_t* row_off = nullptr;
+    int64_t* vtx_off = nullptr;
+    uint64_t* rows = nullptr;
+    int32_t* gid = nullptr;
+    int16_t* col = nullptr;
+    uint64_t* nedges = nullptr;
+    std::vector<int32_t> rank_host;  // rank of each slot's first out-edge (ascending)
+    int64_t bytes = 0;
+};
+
 struct ebbkc_graph {
     int device = 0;
     int32_t n = 0;
@@ -59,6 +78,8 @@ struct ebbkc_graph {
     // per-call scratch (grown on demand, freed by destroy)
     void* scratch = nullptr;
     int32_t* rho_slab = nullptr;      // edge-rank matrices of the EBBkC-T search (allocated on first use)
+    VertexArena varena;               // node-parallel VBBkC roots (built on first use)
+    bool np_active = false;           // the vertex arena is swapped in
     size_t scratch_bytes = 0;
     uint64_t* d_counters = nullptr;   // small device counters
     uint64_t* h_counters = nullptr;   // pinned mirror

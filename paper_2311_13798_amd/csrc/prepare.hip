@@ -599,7 +599,8 @@ ebbkc_status prepare_impl(ebbkc_graph* g, const int32_t* row_ptr, const int32_t*
     // ---- root edge order from a vertex order (ablation orderings): edges in the
     // lexicographic order of their endpoints' positions replace pi_tau; levels
     // and tau stay those of the truss peel (tau + 2 still bounds the clique size)
-    if ((g->opt.ordering == EBBKC_ORDER_COLOR || g->opt.ordering == EBBKC_ORDER_DEGEN_VERTEX) && n > 0) {
+    if ((g->opt.ordering == EBBKC_ORDER_COLOR || g->opt.ordering == EBBKC_ORDER_DEGEN_VERTEX ||
+         g->opt.ordering == EBBKC_ORDER_DEGEN_VERTEX_NP) && n > 0) {
         const int64_t big = (int64_t)n > m ? (int64_t)n : m;
         DBuf<int32_t> vpos, vcol;
         DBuf<uint64_t> k1, k2;

@@ -111,7 +111,10 @@ __global__ __launch_bounds__(256) void k_build(BuildArgs a) {
         if ((int64_t)it >= a.n) break;
         const int32_t s = a.list[it];
         const int32_t e = a.seed_eid[s];
-        const int32_t u = G.eu[e], v = G.ev[e], r = G.rank[e];
+        // a vertex slot is the edge slot with both ends at the vertex: its
+        // row intersected with itself above the threshold is N+(v)
+        const int32_t u = a.seed_rthr ? e : G.eu[e], v = a.seed_rthr ? e : G.ev[e];
+        const int32_t r = a.seed_rthr ? a.seed_rthr[s] : G.rank[e];
 
         // ---- 1. candidates
         const int lu = prefix_after(G.rp, G.rrow, u, r), lv = prefix_after(G.rp, G.rrow, v, r);

@@ -59,10 +59,11 @@ def test_sampled_seed_counts(setup, k):
     assert [int(x) for x in out] == [int(x) for x in rec["counts"]]
 
 
-@pytest.mark.parametrize("name,kw,ks", [("t3", {"t_plex": 3}, (8, 10)), ("vbbkc_ep", {"ordering": 2}, (5, 8, 10))])
+@pytest.mark.parametrize("name,kw,ks", [("t3", {"t_plex": 3}, (8, 10)), ("vbbkc_ep", {"ordering": 2}, (5, 8, 10)),
+                                        ("vbbkc_np", {"ordering": 4}, (5, 8, 10))])
 def test_counts_under_variants(setup, name, kw, ks):
     # 3-plex terminations forced on (the rule picks t = 2 here since 2k <= tau = 82) and the
-    # edge-parallel VBBkC root (degeneracy order): the stored oracle counts at full size
+    # edge- and node-parallel VBBkC roots (degeneracy order): the stored oracle counts at full size
     ebb, fx, g, _ = setup
     o = ebb.ebbkc_default_options()
     for key, v in kw.items():

@@ -2,7 +2,8 @@
 of G, vertices by non-increasing colour, edges in the lexicographic order of their endpoints'
 positions, G's colours kept in every sub-branch) and the edge-parallel VBBkC root (Algorithm VBBkC in
 a degeneracy order with its first two branching steps taken together, Section 6.2 (7)), and EBBkC-T
-(Algorithm EBBkC-T: pi_tau at every level).
+(Algorithm EBBkC-T: pi_tau at every level), and the node-parallel VBBkC root (one root per vertex,
+G[N+(v)]).
 
 The vertex orders are checked against their definitions written out here (sequential greedy
 colouring, level-synchronous core peel), the edge ranks against the lexicographic rule, sub-branch
@@ -136,7 +137,7 @@ def test_counts_equal_under_every_ordering(ebb, name):
     ref = prepared(ebb, g, ebb.ORDER_HYBRID)
     kmax = ref.max_clique_size()
     want = {k: oracle.count(g, k) for k in range(1, kmax + 2)}
-    for ordering in (ebb.ORDER_COLOR, ebb.ORDER_DEGEN_VERTEX, ebb.ORDER_TRUSS):
+    for ordering in (ebb.ORDER_COLOR, ebb.ORDER_DEGEN_VERTEX, ebb.ORDER_TRUSS, ebb.ORDER_DEGEN_VERTEX_NP):
         for kw in ({}, {"rule2": 0}, {"early_termination": 0}):
             if ordering == ebb.ORDER_TRUSS and "rule2" in kw:
                 continue  # no colour rules under EBBkC-T
@@ -213,4 +214,30 @@ def test_truss_order_depth_limit(ebb):
     with pytest.raises(ebb.EbbkcError) as ei:
         G.count(100)
     assert ei.value.status == ebb.E_K_RANGE
+    G.close()
+
+
+def out_degrees(g, pos):
+    eu, ev = oracle.edge_list(g)
+    return np.bincount(np.where(pos[eu] < pos[ev], eu, ev), minlength=g.n)
+
+
+@pytest.mark.parametrize("name", ["er2000", "rmat10"])
+def test_node_parallel_roots(ebb, name):
+    # one root per vertex: N_k equals the oracle's, the vertex order is the edge-parallel one, and rank
+    # ranges / per-seed counts keep the edge roots
+    g = GRAPHS[name]()
+    G = prepared(ebb, g, ebb.ORDER_DEGEN_VERTEX_NP)
+    pos = G.export(ebb.ARR_VERTEX_POS)
+    assert np.array_equal(pos, core_peel_order(g))
+    assert out_degrees(g, pos).max() <= 256
+    for k in range(3, G.max_clique_size() + 2):
+        assert G.count(k) == oracle.count(g, k), k
+    rank = G.export(ebb.ARR_RANK)
+    half = g.m // 2
+    assert G.count_range(5, 0, half) + G.count_range(5, half, g.m) == oracle.count(g, 5)
+    eids = np.arange(min(g.m, 300), dtype=np.int64)
+    out = np.zeros(len(eids), np.uint64)
+    ebb.ebbkc_count_seeds(G.handle, 6, eids, out)
+    assert np.array_equal(out, oracle.seed_counts(g, rank, 6, eids))
     G.close()

@@ -102,3 +102,25 @@ def test_counts_with_three_plex_terminations(setup):
         print(f"case rmat18 t3 k={k}", flush=True)
         assert G.count(k) == fx["counts"][str(k)], k
     G.close()
+
+
+def test_node_parallel_roots_at_full_size(setup):
+    # one root per vertex of the degeneracy order: a vertex with more than 256 later neighbours makes
+    # the count refuse (EBBKC_E_WIDTH); the test decides which from the exported order
+    import oracle
+    ebb, fx, g, _ = setup
+    o = ebb.ebbkc_default_options()
+    o.ordering = ebb.ORDER_DEGEN_VERTEX_NP
+    G = ebb.Graph.from_csr(g, options=o)
+    pos = G.export(ebb.ARR_VERTEX_POS)
+    eu, ev = oracle.edge_list(g)
+    widest = np.bincount(np.where(pos[eu] < pos[ev], eu, ev), minlength=g.n).max()
+    print(f"case rmat18 node-parallel widest root {widest}", flush=True)
+    if widest > 256:
+        with pytest.raises(ebb.EbbkcError) as ei:
+            G.count(5)
+        assert ei.value.status == ebb.E_WIDTH
+    else:
+        assert G.count(5) == fx["counts"]["5"]
+    assert G.count_range(5, 0, g.m // 3) + G.count_range(5, g.m // 3, g.m) == fx["counts"]["5"]
+    G.close()
