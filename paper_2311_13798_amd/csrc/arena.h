@@ -11,6 +11,7 @@ enum : int { ERR_WIDTH = 1, ERR_OVERFLOW = 2, ERR_DEPTH = 4, ERR_CAP = 8 };
 enum : int { OPT_ET = 1, OPT_RULE1 = 4, OPT_RULE2 = 8, OPT_WORK = 16 };
 
 constexpr int MAX_W = 4;              // widest bitmap class: 256 vertices
+constexpr int LIST_FUSED_K = 8;       // listings up to this k sort and hash tuples as they are written
 constexpr int LDS_FRAMES = 12;        // search frames kept in LDS (nodes with l >= 6)
 constexpr int GLOBAL_FRAMES = 124;    // further frames in device memory, per wave
 constexpr int MAX_K = 2 + 2 * (LDS_FRAMES + GLOBAL_FRAMES) + 4;
@@ -120,6 +121,9 @@ struct SearchArgs {
     int32_t* out;
     const int32_t* eu;
     const int32_t* ev;
+    // k <= 8: tuples written sorted and hashed as they are emitted, checksums
+    // [ordered, unordered] added here (null: written as found, sorted later)
+    unsigned long long* list_checksums;
     // batches of graphs: task i belongs to graph task_graph[i], whose arena is
     // views[g] and whose clique size is graph_k[g]; its count is added to
     // graph_total[2g] (low word) / [2g+1] (high word)

@@ -568,6 +568,9 @@ static ebbkc_status run_tasks(ebbkc_graph* g, int32_t k, const int64_t* tsorted,
             }
         }
     }
+    // listings up to k = 8 sort and hash each tuple as it is written
+    unsigned long long* fused = list && k <= LIST_FUSED_K ? (unsigned long long*)(g->d_counters + 8) : nullptr;
+    if (fused) CHKH(hipMemsetAsync(fused, 0, 2 * sizeof(uint64_t), s));
     hipEvent_t ev[MAX_W + 1][2] = {};
     int64_t off = 0;
     for (int W = 1; W <= MAX_W; ++W) {
@@ -594,6 +597,7 @@ static ebbkc_status run_tasks(ebbkc_graph* g, int32_t k, const int64_t* tsorted,
         a.out = out;
         a.eu = g->eu;
         a.ev = g->ev;
+        a.list_checksums = fused;
         a.gframes = gframes;
         CHKH(hipMemsetAsync(a.next, 0, sizeof(uint64_t), s));
         CHKH(hipEventRecord(ev[W][0], s));
@@ -820,9 +824,12 @@ ebbkc_status list_impl(ebbkc_graph* g, int32_t k, int64_t r_begin, int64_t r_end
         }
         *out_written = N;
     }
+    // k_list wrote sorted tuples and their checksums (buffer order) for 3 <= k <= 8
+    const bool fused = k >= 3 && k <= LIST_FUSED_K;
+    const bool resorted = (flags & EBBKC_LIST_SORTED) && N > 1;
     if (N > 0) {
-        CHKH(canon_tuples(d_buf, (int64_t)N, k, s));
-        if ((flags & EBBKC_LIST_SORTED) && N > 1) {
+        if (!fused) CHKH(canon_tuples(d_buf, (int64_t)N, k, s));
+        if (resorted) {
             const int bits = std::max(1, bits_for((uint64_t)(g->n > 0 ? g->n - 1 : 0)));
             const int64_t hn = radix_hist_elems((int64_t)N);
             const size_t bytes = 2 * rnd256(N * 8) + 2 * rnd256(N * 4) + rnd256((size_t)hn * 8) +
@@ -842,8 +849,12 @@ ebbkc_status list_impl(ebbkc_graph* g, int32_t k, int64_t r_begin, int64_t r_end
         }
     }
     if (out_checksums) {
-        CHKH(tuple_checksums(d_buf, (int64_t)N, k, (unsigned long long*)(g->d_counters + 12), s));
-        CHKH(hipMemcpyAsync(out_checksums, g->d_counters + 12, 2 * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+        if (fused && !resorted && N > 0) {
+            CHKH(hipMemcpyAsync(out_checksums, g->d_counters + 8, 2 * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+        } else {
+            CHKH(tuple_checksums(d_buf, (int64_t)N, k, (unsigned long long*)(g->d_counters + 12), s));
+            CHKH(hipMemcpyAsync(out_checksums, g->d_counters + 12, 2 * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+        }
     }
     CHKH(hipStreamSynchronize(s));
     return EBBKC_OK;

@@ -1,7 +1,9 @@
 // list.hip -- k-clique listing: the search of Algorithm EBBkC-C_Rec with the
 // outputs of its terminations (l = 1: S with each vertex; l = 2: S with each
 // edge) written as tuples, plus tuple canonicalisation, lexicographic sorting
-// and the listing checksums.
+// and the listing checksums.  Up to k = 8 a tuple is sorted in registers and
+// hashed as it is written, so no separate canonicalisation or checksum pass
+// reads the buffer again (unless it is sorted afterwards).
 //
 // Every task writes its cliques from the offset its count (same task, same
 // search space) reserved, so the buffer is deterministic.  Pruning Rules (1)
@@ -23,17 +25,88 @@ struct LFrame {
 
 constexpr int LIST_LDS_FRAMES = 16;
 
+template <int N>
+__device__ __forceinline__ void sort_net(int32_t (&v)[N]) {
+    // bitonic sorting network, ascending
+#pragma unroll
+    for (int size = 2; size <= N; size <<= 1)
+#pragma unroll
+        for (int stride = size >> 1; stride > 0; stride >>= 1)
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                const int j = i ^ stride;
+                if (j > i) {
+                    const bool up = (i & size) == 0;
+                    const int32_t a = v[i], b = v[j];
+                    const bool sw = up ? (a > b) : (a < b);
+                    v[i] = sw ? b : a;
+                    v[j] = sw ? a : b;
+                }
+            }
+}
+
+// SplitMix64 output function (the tuple hash of the listing checksums)
+__device__ __forceinline__ uint64_t sm64(uint64_t x) {
+    uint64_t z = x + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// A tuple of at most 8 ids: the node's prefix pre[0..npre) (INT32_MAX
+// beyond) with the leaf ids a (and b when two) inserted, sorted ascending,
+// written at out[idx * k], its hash folded into the [ordered, unordered] sums.
+__device__ __forceinline__ void put_tuple8(int32_t* __restrict__ out, int k, const int32_t (&pre)[8], int npre,
+                                           int32_t a, int32_t b, bool two, uint64_t idx, uint64_t& ho,
+                                           uint64_t& hu) {
+    int32_t v[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] = j == npre ? a : (two && j == npre + 1 ? b : pre[j]);
+    sort_net<8>(v);
+    int32_t* t = out + idx * (uint64_t)k;
+    uint64_t h = (uint64_t)k;
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+        if (j < k) {
+            t[j] = v[j];
+            h = sm64(h ^ (uint64_t)(uint32_t)v[j]);
+        }
+    hu += h;
+    ho += sm64(h ^ sm64(idx));
+}
+
 template <int W>
 struct ListMem {
     uint64_t rows[64 * W][W];
     int32_t gid[64 * W];
+    int32_t eoff[64 * W + 1];  // first tuple of each vertex's edges in the node being written
+    // one-leaf tuples waiting to be sorted and hashed 64 at a time: buffer
+    // index, leaf vertex and the pair (cx, cy) that reached their node
+    uint64_t qidx[128];
+    int16_t qz[128], qx[128], qy[128];
     int16_t col[64 * W];
     LFrame<W> fr[LIST_LDS_FRAMES];
 };
 
+// index of the j-th set bit (from 0) of x, which has more than j set bits
+__device__ __forceinline__ int select_bit(uint64_t x, int j) {
+    int pos = 0;
+#pragma unroll
+    for (int w = 32; w >= 1; w >>= 1) {
+        const uint64_t low = x & ((1ull << w) - 1);
+        const int c = __popcll(low);
+        if (j >= c) {
+            j -= c;
+            x >>= w;
+            pos += w;
+        }
+    }
+    return pos;
+}
+
 }  // namespace
 
-template <int W>
+template <int W, bool FUSED>
 __global__ __launch_bounds__(256) void k_list(SearchArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     ListMem<W>& M = reinterpret_cast<ListMem<W>*>(smem_raw)[threadIdx.x / 64];
@@ -44,6 +117,8 @@ __global__ __launch_bounds__(256) void k_list(SearchArgs a) {
     const int lane = lane_id();
     const int k = a.k, opts = a.opts;
     const bool rule1 = opts & OPT_RULE1, rule2 = opts & OPT_RULE2;
+    constexpr bool fused = FUSED;  // k <= 8
+    uint64_t ho = 0, hu = 0;
 
     for (;;) {
         unsigned long long it = 0;
@@ -85,6 +160,46 @@ __global__ __launch_bounds__(256) void k_list(SearchArgs a) {
             }
             return o;
         };
+        // the same prefix as register values (k <= 8, so at most one frame)
+        auto prefix8 = [&](int32_t (&pre)[8], int depth, int cx, int cy) {
+            int32_t f0 = INT32_MAX, f1 = INT32_MAX, c0 = INT32_MAX, c1 = INT32_MAX;
+            if (depth > 0) {  // frame 0 always lives in LDS
+                f0 = M.gid[M.fr[0].x];
+                f1 = M.gid[M.fr[0].y];
+            }
+            if (cx >= 0) {
+                c0 = M.gid[cx];
+                c1 = M.gid[cy];
+            }
+            const int oc = 2 + 2 * depth;  // where (cx, cy) go
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                pre[j] = j == 0 ? su : j == 1 ? sv : (depth > 0 && j == 2) ? f0 : (depth > 0 && j == 3) ? f1
+                       : (cx >= 0 && j == oc) ? c0 : (cx >= 0 && j == oc + 1) ? c1 : INT32_MAX;
+            return oc + (cx >= 0 ? 2 : 0);
+        };
+        // queued one-leaf tuples (fused): 64 at a time, or all of them before
+        // the frames their prefixes read change
+        int qn = 0;
+        auto flush1 = [&](bool all) {
+            while (qn >= 64 || (all && qn > 0)) {
+                const int take = qn < 64 ? qn : 64;
+                if (lane < take) {
+                    int32_t pre[8];
+                    const int npre = prefix8(pre, sp, M.qx[lane], M.qy[lane]);
+                    put_tuple8(a.out, k, pre, npre, M.gid[M.qz[lane]], 0, false, M.qidx[lane], ho, hu);
+                }
+                wave_sync();
+                for (int i = take + lane; i < qn; i += 64) {  // entries [64, qn) move to [0, qn - 64)
+                    M.qidx[i - take] = M.qidx[i];
+                    M.qz[i - take] = M.qz[i];
+                    M.qx[i - take] = M.qx[i];
+                    M.qy[i - take] = M.qy[i];
+                }
+                wave_sync();
+                qn -= take;
+            }
+        };
         // l = 1 node P reached through (cx, cy) at depth sp: S + {z}
         auto emit1 = [&](const uint64_t (&P)[W], int cx, int cy) {
             const int n = popcW(P);
@@ -95,11 +210,25 @@ __global__ __launch_bounds__(256) void k_list(SearchArgs a) {
                 const bool in = (P[q] >> lane) & 1;
                 const uint64_t mk = ballot(in);
                 if (in) {
-                    int32_t* t = a.out + (base + popc64(mk & lanemask_lt())) * (uint64_t)k;
-                    const int o = prefix(t, sp, cx, cy);
-                    t[o] = M.gid[lane + 64 * q];
+                    const uint64_t idx = base + popc64(mk & lanemask_lt());
+                    if constexpr (fused) {
+                        const int e = qn + popc64(mk & lanemask_lt());
+                        M.qidx[e] = idx;
+                        M.qz[e] = (int16_t)(lane + 64 * q);
+                        M.qx[e] = (int16_t)cx;
+                        M.qy[e] = (int16_t)cy;
+                    } else {
+                        int32_t* t = a.out + idx * (uint64_t)k;
+                        const int o = prefix(t, sp, cx, cy);
+                        t[o] = M.gid[lane + 64 * q];
+                    }
                 }
                 base += popc64(mk);
+                if constexpr (fused) {
+                    qn += popc64(mk);
+                    wave_sync();
+                    flush1(false);
+                }
             }
             pos += n;
         };
@@ -119,6 +248,44 @@ __global__ __launch_bounds__(256) void k_list(SearchArgs a) {
             }
             if (pos + tot > end) { if (lane == 0) atomicOr(a.err, ERR_CAP); pos += tot; return; }
             uint64_t base = pos;
+            if constexpr (fused) {
+                // every lane takes every 64th tuple: vertex z from the edge
+                // offsets, its other end the matching set bit of z's edge mask
+                int32_t pre[8];
+                const int npre = prefix8(pre, sp, cx, cy);
+                uint32_t run = 0;
+#pragma unroll
+                for (int q = 0; q < W; ++q) {
+                    const uint32_t inc = wave_incl_scan(cnt[q]);
+                    M.eoff[lane + 64 * q] = (int32_t)(run + inc - cnt[q]);
+                    run += __shfl(inc, 63, 64);
+                }
+                if (lane == 0) M.eoff[64 * W] = (int32_t)run;
+                wave_sync();
+                for (uint32_t t0 = 0; t0 < (uint32_t)tot; t0 += 64) {
+                    const int t = (int)t0 + lane;
+                    if (t < (int)tot) {
+                        int lo = 0, hi = 64 * W;  // last z with eoff[z] <= t
+                        while (hi - lo > 1) {
+                            const int mid = (lo + hi) >> 1;
+                            if (M.eoff[mid] <= t) lo = mid; else hi = mid;
+                        }
+                        const int z = lo;
+                        int j = t - M.eoff[z], w2 = -1;
+#pragma unroll
+                        for (int wy = 0; wy < W; ++wy) {
+                            const uint64_t bits = P[wy] & M.rows[z][wy] & upper_mask(z, wy);
+                            const int c = popc64(bits);
+                            if (w2 < 0 && j < c) w2 = wy * 64 + select_bit(bits, j);
+                            j -= c;
+                        }
+                        put_tuple8(a.out, k, pre, npre, M.gid[z], M.gid[w2], true, base + (uint64_t)t, ho, hu);
+                    }
+                }
+                wave_sync();
+                pos += tot;
+                return;
+            }
 #pragma unroll
             for (int q = 0; q < W; ++q) {
                 const uint32_t inc = wave_incl_scan(cnt[q]);
@@ -189,6 +356,7 @@ __global__ __launch_bounds__(256) void k_list(SearchArgs a) {
                     for (int w = 0; w < W; ++w) R[w] = P[w] & M.rows[x][w] & upper_mask(x, w);
                 }
                 if (y < 0) {
+                    if constexpr (fused) flush1(true);
                     if (sp == 0) break;
                     --sp;
                     LFrame<W>& F = FR(sp);
@@ -225,6 +393,7 @@ __global__ __launch_bounds__(256) void k_list(SearchArgs a) {
                     if (lane == 0) atomicOr(a.err, ERR_DEPTH);
                     continue;
                 }
+                if constexpr (fused) flush1(true);
                 if (lane == 0 || sp >= LIST_LDS_FRAMES) {
                     LFrame<W>& F = FR(sp);
 #pragma unroll
@@ -241,8 +410,17 @@ __global__ __launch_bounds__(256) void k_list(SearchArgs a) {
                 l = lc;
             }
         }
+        if constexpr (fused) flush1(true);
         if (pos != end && lane == 0) atomicOr(a.err, ERR_CAP);
         wave_sync();
+    }
+    if (fused) {
+        ho = wave_sum(ho);
+        hu = wave_sum(hu);
+        if (lane == 0) {
+            atomicAdd(&a.list_checksums[0], (unsigned long long)ho);
+            atomicAdd(&a.list_checksums[1], (unsigned long long)hu);
+        }
     }
 }
 
@@ -250,25 +428,6 @@ __global__ __launch_bounds__(256) void k_list(SearchArgs a) {
 
 namespace {
 
-template <int N>
-__device__ __forceinline__ void sort_net(int32_t (&v)[N]) {
-    // bitonic sorting network, ascending
-#pragma unroll
-    for (int size = 2; size <= N; size <<= 1)
-#pragma unroll
-        for (int stride = size >> 1; stride > 0; stride >>= 1)
-#pragma unroll
-            for (int i = 0; i < N; ++i) {
-                const int j = i ^ stride;
-                if (j > i) {
-                    const bool up = (i & size) == 0;
-                    const int32_t a = v[i], b = v[j];
-                    const bool sw = up ? (a > b) : (a < b);
-                    v[i] = sw ? b : a;
-                    v[j] = sw ? a : b;
-                }
-            }
-}
 
 template <int N>
 __global__ void k_canon(int32_t* __restrict__ buf, int64_t n, int k) {
@@ -308,12 +467,6 @@ __global__ void k_gather_tuples(const int32_t* __restrict__ src, const uint32_t*
     }
 }
 
-__device__ __forceinline__ uint64_t sm64(uint64_t x) {
-    uint64_t z = x + 0x9E3779B97F4A7C15ull;
-    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-    return z ^ (z >> 31);
-}
 
 // [ordered, unordered] checksums (sums mod 2^64)
 __global__ void k_checksums(const int32_t* __restrict__ buf, int64_t n, int k, unsigned long long* __restrict__ out) {
@@ -353,9 +506,9 @@ inline unsigned gridn(int64_t n) {
     return (unsigned)b;
 }
 
-template <int W>
+template <int W, bool FUSED>
 hipError_t launch_list_w(const SearchArgs& a, int cus, hipStream_t s) {
-    auto kern = k_list<W>;
+    auto kern = k_list<W, FUSED>;
     const size_t smem = 4 * sizeof(ListMem<W>);
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
     if (e != hipSuccess) return e;
@@ -374,11 +527,12 @@ hipError_t launch_list_w(const SearchArgs& a, int cus, hipStream_t s) {
 
 hipError_t launch_list(int W, const SearchArgs& a, int cus, hipStream_t s) {
     if (a.ntasks <= 0) return hipSuccess;
+    const bool fused = a.list_checksums != nullptr;
     switch (W) {
-        case 1: return launch_list_w<1>(a, cus, s);
-        case 2: return launch_list_w<2>(a, cus, s);
-        case 3: return launch_list_w<3>(a, cus, s);
-        case 4: return launch_list_w<4>(a, cus, s);
+        case 1: return fused ? launch_list_w<1, true>(a, cus, s) : launch_list_w<1, false>(a, cus, s);
+        case 2: return fused ? launch_list_w<2, true>(a, cus, s) : launch_list_w<2, false>(a, cus, s);
+        case 3: return fused ? launch_list_w<3, true>(a, cus, s) : launch_list_w<3, false>(a, cus, s);
+        case 4: return fused ? launch_list_w<4, true>(a, cus, s) : launch_list_w<4, false>(a, cus, s);
     }
     return hipErrorInvalidValue;
 }
