@@ -55,7 +55,6 @@ struct ebbkc_graph {
     int32_t* subsize = nullptr; // m: |V(g_i)| per edge (filled on demand)
     int32_t* vpos = nullptr;    // n: position in the root vertex order (orderings COLOR, DEGEN_VERTEX)
     int32_t* vcol = nullptr;    // n: greedy colour of G (ordering COLOR)
-    std::vector<int32_t> lvl_by_rank; // host copy: level of the edge at each rank
     bool subsize_ready = false;
 
     // sub-branch arena (built on the first count with k >= 4)

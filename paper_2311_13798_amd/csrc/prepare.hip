@@ -293,12 +293,6 @@ __global__ void k_byrank(const int32_t* __restrict__ rank, int64_t m, int32_t* _
         byrank[rank[e]] = (int32_t)e;
 }
 
-__global__ void k_level_by_rank(const int32_t* __restrict__ byrank, const int32_t* __restrict__ level, int64_t m,
-                                int32_t* __restrict__ out) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x)
-        out[i] = level[byrank[i]];
-}
-
 // ---- vertex orders for the root edge order of the ablation orderings
 
 // Greedy colouring in the visiting order (degree desc, id asc), one wave per
@@ -722,9 +716,6 @@ ebbkc_status prepare_impl(ebbkc_graph* g, const int32_t* row_ptr, const int32_t*
     CHK(byrank.alloc(m));
     if (m) {
         hipLaunchKernelGGL(k_byrank, dim3(grid_for(m)), dim3(TB), 0, s, rank.p, m, byrank.p);
-        hipLaunchKernelGGL(k_level_by_rank, dim3(grid_for(m)), dim3(TB), 0, s, byrank.p, level.p, m, flag.p);
-        g->lvl_by_rank.resize((size_t)m);
-        CHK(hipMemcpyAsync(g->lvl_by_rank.data(), flag.p, sizeof(int32_t) * (size_t)m, hipMemcpyDeviceToHost, s));
     }
     CHK(hipGetLastError());
     CHK(hipEventRecord(ev1, s));
