@@ -18,8 +18,12 @@
  *      edges among them ranked after e_i.  g_i is coloured greedily, ordered
  *      by non-increasing colour, oriented into a DAG, and searched with
  *      pruning Rules (1) and (2) of Section 4.3; a candidate set that is a
- *      clique or a 2-plex is finished in closed form (Section 5, Algorithm
- *      kC2Plex).
+ *      clique, a 2-plex or (per the t rule of Section 6.1) a 3-plex is
+ *      finished in closed form (Section 5, Algorithms kC2Plex, kCtPlex).
+ *
+ * ebbkc_options.ordering selects the paper's other variants on the same
+ * engine instead (EBBkC-C, EBBkC-T, and VBBkC's edge- and node-parallel
+ * schemes); every variant gives the same counts and listings.
  *
  * Conventions
  *   - The graph is simple and undirected (Section 2), given as int32 CSR
@@ -175,7 +179,8 @@ ebbkc_status ebbkc_count128(ebbkc_graph *g, int32_t k, uint64_t out_count[2], vo
 ebbkc_status ebbkc_max_clique_size(ebbkc_graph *g, int32_t *out, void *stream);
 
 /* Number of k-cliques whose seed edge (the edge of the clique that comes
- * first in pi_tau) has rank in [r_begin, r_end).  Summed over a partition of
+ * first in the initial branch's edge order, pi_tau by default) has rank in
+ * [r_begin, r_end).  Summed over a partition of
  * [0, m) this is the full count (every k-clique is listed exactly once,
  * Section 4.1).  k >= 3. */
 ebbkc_status ebbkc_count_range(ebbkc_graph *g, int32_t k, int64_t r_begin, int64_t r_end,
