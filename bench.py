@@ -274,6 +274,8 @@ def main():
                    "n": g.n, "m": g.m, "tau": int(info.tau), "peel_rounds": int(info.rounds), "ks": ks},
         "counts": {str(k): v for k, v in counts.items()},
         "prepare_ms": round(float(np.mean([r[3] for r in runs])), 3),
+        # space (Section 6.2 (8)): the prepared graph's device arrays plus its sub-branch arena
+        "device_bytes": int(info.device_bytes),
         "branch_ms_by_class": {str(k): [round(x, 3) for x in np.mean([np.array(r[1][k]) for r in runs], axis=0)]
                                for k in ks},
         "roofline": roofline,
