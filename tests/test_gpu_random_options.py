@@ -87,3 +87,28 @@ def test_random_listings(ebb, seed):
                 got = buf[:c].cpu().numpy()
                 assert (np.diff(got, axis=1) > 0).all()
     G.close()
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_random_batches_and_rank_partitions(ebb, seed):
+    # graphs prepared under random options, counted together in one fused batch (replayed from the
+    # HIP graph twice) and alone over a random partition of the rank range; all equal the oracle
+    rng = random.Random(3000 + seed)
+    gs, Gs, ks = [], [], []
+    for _ in range(rng.randint(3, 8)):
+        kind, g = random_graph(rng)
+        o = random_options(ebb, rng)
+        G = ebb.Graph.from_csr(g, options=o)
+        k = rng.randint(3, max(3, G.max_clique_size()))
+        gs.append(g)
+        Gs.append(G)
+        ks.append(k)
+    want = [oracle.count(g, k) for g, k in zip(gs, ks)]
+    B = ebb.Batch(Gs, ks)
+    for rep in range(2):
+        assert list(B.run(use_graph=True)) == want, (seed, rep)
+    B.close()
+    for g, G, k, w in zip(gs, Gs, ks, want):
+        cuts = sorted({0, g.m, *[rng.randint(0, g.m) for _ in range(3)]})
+        assert sum(G.count_range(k, a, b) for a, b in zip(cuts, cuts[1:])) == w, (seed, k)
+        G.close()
