@@ -408,7 +408,7 @@ const int lane = lane_id();
 }  // namespace
 
 template <int W, bool LIST>
-__global__ __launch_bounds__(256, (W == 1 ? 4 : (W <= 3 ? 3 : 2))) void k_search(SearchArgs a) {
+__global__ __launch_bounds__(256, (W <= 2 ? 4 : (W <= 3 ? 3 : 2))) void k_search(SearchArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     SearchMem<W>& M = reinterpret_cast<SearchMem<W>*>(smem_raw)[threadIdx.x / 64];
     Frame<W>* gfr = a.gframes ? reinterpret_cast<Frame<W>*>(a.gframes) +
