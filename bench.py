@@ -5,36 +5,61 @@ One step = the whole hot path over the resident input: ebbkc_prepare on the CSR 
 for every k of the workload (5, 6, 7, 8, 9; the first count also builds the sub-branch arena).
 value = k-cliques counted per second = (sum over k of N_k) / step time.
 
+Wall budget.  The run is bounded by --budget-s seconds from process start (default 450).  --warmup
+and --steps are upper bounds: warmup steps beyond the first run only while the timed steps still
+fit, and a timed step starts only while it is expected to end before the measurement deadline
+(--core-s, default 300 s from process start; at least one timed step always runs).  "steps" and
+"warmup" on the JSON line are the numbers actually run, "steps_requested" / "warmup_requested" the
+numbers asked for.  Every leg after the measurement runs only if its estimated time fits what is
+left of the budget; a leg left out is reported as {"skipped": reason}.
+
 Also reported on the same JSON line:
   roofline      the dominant branch-kernel launch (the bitmap width class launch with the largest
-                device time in the timed step): its algorithmic 64-bit word operations (AND +
+                device time in the timed steps): its algorithmic 64-bit word operations (AND +
                 popcount of one candidate-bitmap word; counted by the library's per-launch work
                 counters, on in the timed run: they cost under 1 %) divided by its device time
                 (HIP events on the launch stream).  Bound: VALU ("alu"); peak derived from
                 256 CUs x 64 int32 lanes/clock x 2.4 GHz = 39.3 T lane-ops/s, four lane-ops per
                 word-op (two 32-bit ANDs, two 32-bit popcounts) -> 9.83 T word-ops/s.
                 traffic: HBM bytes per launch from rocprofv3 FETCH_SIZE + WRITE_SIZE (KiB, scaled
-                by the same counters on a copy kernel of known size) when a committed record
-                for the current kernel source exists, else null.
+                by the same counters on a copy kernel of known size) when the committed record
+                (profiles/search_rmat18_k9_traffic.json) was taken on the current kernel source,
+                else null.
   cpu_baseline  the CPU oracle (degeneracy-ordered vertex branch and bound) timed on the host
-                cores on a bounded sample of the same workload (the full k = 5 and k = 6 counts).
+                cores on a bounded sample of the same workload (the full k = 5 and k = 6 counts),
+                with the GPU's time on the same sample (from the timed steps) beside it.
   listing       every 5-clique of the workload (5.5e10 tuples, 1.1 TB) listed rank-range chunk by
                 chunk into one 80 GB device buffer: tuples/s and GB/s written (HBM-write bound).
   batched       many small graphs with per-graph k: one launch per (graph, k) vs the fused
                 batch (one persistent launch per width class, replayed from a HIP graph).
+  served        Poisson request streams over a mixed resident catalogue against the native
+                continuous-batching server: p50/p99 latency from arrival to result, k-cliques per
+                second, every result equal to the same request run alone.
   ablation      (--ablation) the same engine under the paper's variants: orderings C, T and the
                 edge- and node-parallel VBBkC roots, Rule (2) off, early termination off, t = 1 / 3.
-  served        Poisson request streams (50, 200, 1000 requests/s) over a mixed resident catalogue
-                against the native continuous-batching server: p50/p99 latency from arrival to
-                result, k-cliques per second, every result equal to the same request run alone.
+
+Counter modes (not part of the default run):
+  --traffic-run               a 1 GiB device copy (counter calibration), then the workload's k = 9
+                              count after the k = 4 count that builds the arena; run it under
+                              rocprofv3 --pmc FETCH_SIZE, and again under --pmc WRITE_SIZE.
+  --traffic-record F W OUT    reads those two runs' counter CSVs (directories F and W) and writes
+                              the per-launch HBM bytes of the search kernels to OUT, with the hash
+                              of the kernel sources they belong to.
 """
 from __future__ import annotations
 
-import argparse
-import json
-import os
-import sys
 import time
+
+T_START = time.time()  # the wall budget counts from here, before the heavy imports
+
+import argparse  # noqa: E402
+import csv  # noqa: E402
+import glob  # noqa: E402
+import hashlib  # noqa: E402
+import json  # noqa: E402
+import os  # noqa: E402
+import re  # noqa: E402
+import sys  # noqa: E402
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -42,10 +67,27 @@ sys.path.insert(0, ROOT)
 METRIC = "k-cliques counted/sec (R-MAT s18, k=5..9) vs plain kernel; p50/p99 request latency"
 PEAK_WORD_OPS = 256 * 64 * 2.4e9 / 4 / 1e12  # T word-ops/s
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "search_rmat18_k9_traffic.json")
+CSRC = os.path.join(ROOT, "paper_2311_13798_amd", "csrc")
+COPY_BYTES = 1 << 30
 
 
 def log(msg):
-    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+    print(f"[bench {time.time() - T_START:7.1f}s] {msg}", file=sys.stderr, flush=True)
+
+
+def left(budget_s):
+    return T_START + budget_s - time.time()
+
+
+# ---------------------------------------------------------------- HBM traffic record
+
+def source_sha256() -> str:
+    """Hash of the search kernel's sources (the traffic record is valid only for these)."""
+    h = hashlib.sha256()
+    for f in ("search.hip", "arena.h", "device_util.h", "common.h"):
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
 
 
 def traffic_for(kernel: str, k: int):
@@ -54,12 +96,82 @@ def traffic_for(kernel: str, k: int):
     if not os.path.exists(TRAFFIC_RECORD):
         return None
     rec = json.load(open(TRAFFIC_RECORD))
-    from paper_2311_13798_amd.traffic_probe import source_sha256
     if rec.get("source_sha256") != source_sha256():
         return None
     e = rec.get("launches", {}).get(f"{kernel}@k={k}")
     return None if e is None else e.get("hbm_bytes")
 
+
+def traffic_run(k: int = 9):
+    import torch
+
+    import paper_2311_13798_amd as ebb
+    from graphgen import configs
+
+    torch.cuda.set_device(0)
+    n = COPY_BYTES // 4  # float32 elements
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.mul(src, 2.0, out=dst)
+    torch.cuda.synchronize()
+    print("copy done", flush=True)
+    g = configs.rmat18()
+    G = ebb.Graph.from_csr(g)
+    G.count(4)
+    print(f"k={k} count={G.count(k)} classes_ms={G.last_timing()}", flush=True)
+    G.close()
+
+
+def _per_dispatch(run_dir: str, counter: str):
+    """(kernel name, dispatch id) -> counter value summed over the CSV rows of that dispatch."""
+    files = glob.glob(os.path.join(run_dir, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        raise FileNotFoundError(f"no counter_collection.csv under {run_dir}")
+    out = {}
+    for f in files:
+        with open(f, newline="") as fh:
+            for row in csv.DictReader(fh):
+                if row.get("Counter_Name") != counter:
+                    continue
+                key = (row["Kernel_Name"], int(row.get("Dispatch_Id", 0)))
+                out[key] = out.get(key, 0.0) + float(row["Counter_Value"])
+    return out
+
+
+def traffic_record(fetch_dir: str, write_dir: str, out_json: str, k: int = 9, command: str = ""):
+    fetch = _per_dispatch(fetch_dir, "FETCH_SIZE")
+    write = _per_dispatch(write_dir, "WRITE_SIZE")
+
+    def copy_kib(d):
+        vals = [v for (name, _), v in d.items() if "elementwise" in name and "MulFunctor" in name]
+        if not vals:
+            raise ValueError("the copy kernel was not profiled")
+        return max(vals)
+
+    ff = COPY_BYTES / (copy_kib(fetch) * 1024.0)
+    wf = COPY_BYTES / (copy_kib(write) * 1024.0)
+    launches = {}
+    for (name, _), fk in sorted(fetch.items(), key=lambda kv: kv[0][1]):
+        mm = re.search(r"k_search<(\d), false>", name)
+        if not mm:
+            continue
+        wk = next((v for (n2, _), v in write.items() if n2 == name), None)
+        if wk is None:
+            continue
+        key = f"ebb::k_search<{mm.group(1)}, false>@k={k}"
+        launches[key] = {"fetch_KiB": fk, "write_KiB": wk,
+                         "hbm_bytes": int(round(fk * 1024.0 * ff + wk * 1024.0 * wf))}
+    rec = {"source_sha256": source_sha256(), "command": command,
+           "copy_kernel": {"bytes_read": COPY_BYTES, "bytes_written": COPY_BYTES,
+                           "fetch_KiB": copy_kib(fetch), "write_KiB": copy_kib(write),
+                           "fetch_scale": ff, "write_scale": wf},
+           "launches": launches}
+    with open(out_json, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    return rec
+
+
+# ---------------------------------------------------------------- legs after the measurement
 
 def full_listing(ebb, torch, rp, ci, g, k=5, cap=4_000_000_000):
     """Every k-clique of the workload listed into one reused device buffer of cap tuples (80 GB at
@@ -85,20 +197,20 @@ def full_listing(ebb, torch, rp, ci, g, k=5, cap=4_000_000_000):
             "order": "unsorted (tuples ascending inside, buffer order by seed rank)"}
 
 
-def systems_forms(ebb, np, torch, configs):
-    """Batched and served forms on graphs shaped like the batched workload (n scaled by 0.1)."""
-    from paper_2311_13798_amd.serve import Server, poisson_requests, summarize
-    params = configs.batch_params(4096)[:512]
+def batched_leg(ebb, torch, configs, ngraphs=512, scale=0.1):
+    """One launch per (graph, k) against the fused batch on graphs of the batched workload with n
+    scaled by `scale`: k-cliques/s of each, unprofiled, at identical counts."""
+    params = configs.batch_params(4096)[:ngraphs]
     gs, ks = [], []
     for p in params:
         q = dict(p)
-        q["n"] = max(50, int(p["n"] * 0.1))
+        q["n"] = max(50, int(p["n"] * scale))
         q["clique"] = min(p["clique"], q["n"])
         gs.append(configs.batch_graph(q))
         ks.append(int(p["k"]))
     Gs = [ebb.Graph.from_csr(g) for g in gs]
     torch.cuda.synchronize()
-    plain = [G.count(k) for G, k in zip(Gs, ks)]  # also builds every arena
+    [G.count(k) for G, k in zip(Gs, ks)]  # also builds every arena
     t = time.perf_counter()
     plain = [G.count(k) for G, k in zip(Gs, ks)]
     t_plain = time.perf_counter() - t
@@ -109,15 +221,21 @@ def systems_forms(ebb, np, torch, configs):
     t_batch = time.perf_counter() - t
     B.close()
     tot = sum(plain)
-    batched = {"graphs": len(Gs), "workload": "512 graphs of the batched workload with n scaled by 0.1 "
-                                              "(n U{50..500}, p U[0.005,0.2], 20% with a planted 20..40-clique, "
-                                              "k U{3..10})",
-               "kcliques": tot, "plain_s": round(t_plain, 5), "batched_s": round(t_batch, 5),
-               "plain_kcliques_per_s": tot / t_plain, "batched_kcliques_per_s": tot / t_batch,
-               "vs_plain": round(t_plain / t_batch, 3), "identical": got == plain}
+    out = {"graphs": len(Gs),
+           "workload": f"{ngraphs} graphs of the batched workload with n scaled by {scale} "
+                       "(p U[0.005,0.2], 20% with a planted 20..40-clique, k U{3..10})",
+           "kcliques": tot, "plain_s": round(t_plain, 5), "batched_s": round(t_batch, 5),
+           "plain_kcliques_per_s": tot / t_plain, "batched_kcliques_per_s": tot / t_batch,
+           "vs_plain": round(t_plain / t_batch, 3), "identical": got == plain}
     log(f"batched: plain {t_plain:.3f}s fused {t_batch:.3f}s identical={got == plain}")
-    # served: a mixed catalogue resident (R-MAT s12, s13, Chung-Lu 1e4..3e5, ER(2000, 0.01) and 64 of
-    # the batched graphs), Poisson requests with k U{3..12}; R-MAT s13 at k = 12 takes ~2.3 s alone
+    return out, Gs
+
+
+def served_leg(ebb, configs, Gs, rates, budget_s, est_per_rate_s=25.0):
+    """Poisson request streams over a resident catalogue (R-MAT s12, s13, Chung-Lu 1e4..3e5,
+    ER(2000, 0.01) and 64 of the batched graphs), k U{3..12}; every result compared with the same
+    request run alone."""
+    from paper_2311_13798_amd.serve import Server, poisson_requests, summarize
     named = [("rmat12", configs.rmat_scale(12)), ("rmat13", configs.rmat_scale(13)),
              ("cl1e4", configs.cl_planted(10000)), ("cl3e4", configs.cl_planted(30000)),
              ("cl1e5", configs.cl_planted(100000)), ("cl3e5", configs.cl_planted(300000)),
@@ -127,7 +245,10 @@ def systems_forms(ebb, np, torch, configs):
     alone = {(i, k): G.count(k) for i, G in enumerate(cat) for k in range(3, 13)}
     served = {"catalogue": [n for n, _ in named] + ["64 batched-workload graphs (n scaled by 0.1)"],
               "k": "U{3..12}", "budget_bytes": 1 << 34, "epochs_in_flight": 3, "rates": {}}
-    for rate, count in ((50.0, 500), (200.0, 1000), (1000.0, 2000)):
+    for rate, count in rates:
+        if left(budget_s) < est_per_rate_s:
+            served["rates"][str(int(rate))] = {"skipped": "wall budget"}
+            continue
         S = Server(cat, 1 << 34)
         reqs = poisson_requests(rate=rate, count=count, n_graphs=len(cat), k_lo=3, k_hi=12, seed=1)
         res = S.run_stream(reqs)
@@ -142,9 +263,7 @@ def systems_forms(ebb, np, torch, configs):
         log(f"served {rate:.0f} req/s: p50 {s['p50_ms']:.3f} ms p99 {s['p99_ms']:.3f} ms identical={same}")
     for G in extra:
         G.close()
-    for G in Gs:
-        G.close()
-    return batched, served
+    return served
 
 
 def ablation(ebb, torch, configs, graphgen):
@@ -187,22 +306,57 @@ def ablation(ebb, torch, configs, graphgen):
     return {"unit": "ms per count", "variants": {v: kw for v, kw in variants}, "results": out}
 
 
+# ---------------------------------------------------------------- the measurement
+
+def plan_warmups(requested: int, done: int, step_s: float, core_left: float, steps_requested: int) -> bool:
+    """Whether another warmup step runs: the first always does (if any was asked for); later ones
+    only while the requested timed steps would still fit after it."""
+    if done >= requested:
+        return False
+    if done == 0:
+        return True
+    return core_left > step_s * (1 + steps_requested)
+
+
+def plan_timed(done: int, steps_requested: int, step_s: float, core_left: float) -> bool:
+    """Whether another timed step starts: the first always does; later ones only while the step is
+    expected to end before the measurement deadline."""
+    if done >= steps_requested:
+        return False
+    if done == 0:
+        return True
+    return core_left > step_s
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1)
-    ap.add_argument("--warmup", type=int, default=0)
+    ap.add_argument("--steps", type=int, default=3, help="timed steps (an upper bound under the wall budget)")
+    ap.add_argument("--warmup", type=int, default=1, help="warmup steps (an upper bound under the wall budget)")
+    ap.add_argument("--budget-s", type=float, default=450.0, help="wall budget of the whole run from process start")
+    ap.add_argument("--core-s", type=float, default=300.0, help="deadline of the timed steps from process start")
     ap.add_argument("--ks", default="5,6,7,8,9", help="comma-separated k values counted in every step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-systems", action="store_true", help="skip the batched and served forms")
     ap.add_argument("--no-list", action="store_true", help="skip the full k = 5 listing")
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--ablation", action="store_true", help="also time the ordering / rule / termination variants")
+    ap.add_argument("--traffic-run", action="store_true", help="counter mode: copy calibration + k = 9 count")
+    ap.add_argument("--traffic-record", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "OUT_JSON"))
+    ap.add_argument("--traffic-k", type=int, default=9)
+    ap.add_argument("--traffic-command", default="")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU sharding of this "
               "path is a design note, not a built feature", file=sys.stderr)
         sys.exit(2)
+    if args.traffic_record:
+        rec = traffic_record(*args.traffic_record, k=args.traffic_k, command=args.traffic_command)
+        print(json.dumps(rec, indent=1))
+        return
+    if args.traffic_run:
+        traffic_run(args.traffic_k)
+        return
     ks = [int(x) for x in args.ks.split(",") if x]
 
     import numpy as np
@@ -216,96 +370,132 @@ def main():
     rp = torch.from_numpy(g.row_ptr).cuda()
     ci = torch.from_numpy(g.col_idx).cuda()
     torch.cuda.synchronize()
+    log(f"setup done: n={g.n} m={g.m}")
     opts = ebb.ebbkc_default_options()
     opts.count_work = 1
 
     def step(tag):
+        t0 = time.perf_counter()
         G = ebb.Graph(rp, ci, g.n, options=opts)
-        counts, kms, work = {}, {}, {}
+        t_prep = time.perf_counter() - t0
+        counts, kms, work, wall = {}, {}, {}, {}
         for k in ks:
             t = time.perf_counter()
             counts[k] = G.count(k)
+            wall[k] = time.perf_counter() - t
             kms[k] = G.last_timing()
             work[k] = [G.last_work_class(W) for W in (1, 2, 3, 4)]
-            log(f"{tag} k={k} N_k={counts[k]} {time.perf_counter() - t:.3f}s")
-        prep = G.info.prepare_ms
+            log(f"{tag} k={k} N_k={counts[k]} {wall[k]:.3f}s")
         info = G.info
         G.close()
-        return counts, kms, work, prep, info
+        torch.cuda.synchronize()
+        return dict(counts=counts, kms=kms, work=work, wall=wall, prep_ms=info.prepare_ms, prep_wall=t_prep,
+                    info=info, total_s=time.perf_counter() - t0)
 
-    for i in range(args.warmup):
-        step(f"warmup {i}")
+    step_s = 0.0
+    warm = 0
+    while plan_warmups(args.warmup, warm, step_s, left(args.core_s), args.steps):
+        r = step(f"warmup {warm}")
+        step_s = max(step_s, r["total_s"])
+        warm += 1
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     runs = []
-    for i in range(args.steps):
-        runs.append(step(f"step {i}"))
+    while plan_timed(len(runs), args.steps, step_s, left(args.core_s)):
+        runs.append(step(f"step {len(runs)}"))
+        step_s = max(step_s, runs[-1]["total_s"]) if warm else runs[-1]["total_s"]
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    counts, _, _, _, info = runs[-1]
+    nsteps = len(runs)
+    counts, info = runs[-1]["counts"], runs[-1]["info"]
+    assert all(r["counts"] == counts for r in runs), "counts differ between steps"
     total = sum(counts.values())
-    ms_per_step = 1000.0 * elapsed / args.steps
+    ms_per_step = 1000.0 * elapsed / nsteps
+    log(f"timed {nsteps} steps after {warm} warmup: {ms_per_step / 1e3:.2f} s per step")
 
     # dominant launch: the (k, width class) launch with the largest mean device time
     best = None
     for k in ks:
-        per_class = np.mean([np.array(r[1][k]) for r in runs], axis=0)
+        per_class = np.mean([np.array(r["kms"][k]) for r in runs], axis=0)
         for W in range(1, 5):
             if best is None or per_class[W - 1] > best[2]:
                 best = (k, W, float(per_class[W - 1]))
     kd, wd, dom_ms = best
-    word_ops = int(np.mean([r[2][kd][wd - 1][2] for r in runs]))
+    word_ops = int(np.mean([r["work"][kd][wd - 1][2] for r in runs]))
     achieved = word_ops / (dom_ms / 1e3) / 1e12 if dom_ms > 0 else 0.0
     kernel = f"ebb::k_search<{wd}, false>"
     roofline = {"bound": "alu", "kernel": kernel, "k": kd, "achieved": round(achieved, 4),
                 "peak": round(PEAK_WORD_OPS, 3), "unit": "T word-ops/s", "frac": round(achieved / PEAK_WORD_OPS, 5),
                 "traffic": traffic_for(kernel, kd), "word_ops_per_launch": word_ops,
-                "nodes_per_launch": int(np.mean([r[2][kd][wd - 1][1] for r in runs])),
-                "tasks_per_launch": int(np.mean([r[2][kd][wd - 1][0] for r in runs])),
+                "nodes_per_launch": int(np.mean([r["work"][kd][wd - 1][1] for r in runs])),
+                "tasks_per_launch": int(np.mean([r["work"][kd][wd - 1][0] for r in runs])),
                 "launch_ms": round(dom_ms, 3)}
 
     line = {
         "metric": METRIC, "value": total / (ms_per_step / 1e3), "unit": "k-cliques/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True,
+        "steps": nsteps, "warmup": warm, "steps_requested": args.steps, "warmup_requested": args.warmup,
+        "ms_per_step": round(ms_per_step, 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
         "config": {"workload": "R-MAT scale 18, edge factor 16, (a,b,c,d)=(0.57,0.19,0.19,0.05), seed 1, "
                                "symmetrised, deduplicated, loops dropped; step = prepare + count at k=" +
                                ",".join(map(str, ks)),
                    "n": g.n, "m": g.m, "tau": int(info.tau), "peel_rounds": int(info.rounds), "ks": ks},
+        "wall_budget": {"budget_s": args.budget_s, "core_s": args.core_s},
         "counts": {str(k): v for k, v in counts.items()},
-        "prepare_ms": round(float(np.mean([r[3] for r in runs])), 3),
+        "prepare_ms": round(float(np.mean([r["prep_ms"] for r in runs])), 3),
+        "count_wall_s": {str(k): round(float(np.mean([r["wall"][k] for r in runs])), 4) for k in ks},
         # space (Section 6.2 (8)): the prepared graph's device arrays plus its sub-branch arena
         "device_bytes": int(info.device_bytes),
-        "branch_ms_by_class": {str(k): [round(x, 3) for x in np.mean([np.array(r[1][k]) for r in runs], axis=0)]
+        "branch_ms_by_class": {str(k): [round(x, 3) for x in np.mean([np.array(r["kms"][k]) for r in runs], axis=0)]
                                for k in ks},
         "roofline": roofline,
     }
 
+    if not args.no_cpu_baseline:
+        if left(args.budget_s) < 60:
+            line["cpu_baseline"] = {"skipped": "wall budget"}
+        else:
+            import oracle
+            th = args.cpu_threads or max(1, min(16, os.cpu_count() or 1))
+            got, secs = {}, {}
+            for k in (5, 6):  # about 20 s of oracle work on 16 host threads
+                t = time.perf_counter()
+                got[k] = oracle.count(g, k, threads=th)
+                secs[k] = time.perf_counter() - t
+            n_all, dt = sum(got.values()), sum(secs.values())
+            cb = {"value": n_all / dt, "unit": "k-cliques/s", "cores": th, "kind": "oracle",
+                  "sample": "full k=5 and k=6 counts of the same graph (" +
+                            ", ".join(f"N_{k}={got[k]} in {secs[k]:.2f} s" for k in got) +
+                            "); degeneracy-ordered vertex branch and bound, uint64",
+                  "agrees_with_gpu": all(got[k] == counts[k] for k in got if k in counts)}
+            if 5 in ks and 6 in ks:
+                # the GPU on the same sample, from the timed steps: the k = 5 and k = 6 counts (the
+                # first includes the sub-branch arena build) with and without the prepare
+                gc = float(np.mean([r["wall"][5] + r["wall"][6] for r in runs]))
+                gp = float(np.mean([r["prep_wall"] for r in runs]))
+                cb["gpu_same_sample"] = {"count_s": round(gc, 4), "prepare_s": round(gp, 4),
+                                         "kcliques_per_s": n_all / gc, "kcliques_per_s_with_prepare": n_all / (gc + gp)}
+            line["cpu_baseline"] = cb
+            log(f"cpu baseline {n_all / dt:.3e} k-cliques/s on {th} threads")
+
     if not args.no_list:
-        line["listing"] = full_listing(ebb, torch, rp, ci, g)
+        line["listing"] = full_listing(ebb, torch, rp, ci, g) if left(args.budget_s) > 60 else {
+            "skipped": "wall budget"}
 
     if not args.no_systems:
-        line["batched"], line["served"] = systems_forms(ebb, np, torch, configs)
+        if left(args.budget_s) > 70:
+            line["batched"], Gs = batched_leg(ebb, torch, configs)
+            line["served"] = served_leg(ebb, configs, Gs, ((50.0, 500), (200.0, 1000), (1000.0, 2000)),
+                                        args.budget_s)
+            for G in Gs:
+                G.close()
+        else:
+            line["batched"] = line["served"] = {"skipped": "wall budget"}
 
     if args.ablation:
         import graphgen
         line["ablation"] = ablation(ebb, torch, configs, graphgen)
-
-    if not args.no_cpu_baseline:
-        import oracle
-        th = args.cpu_threads or max(1, min(16, os.cpu_count() or 1))
-        got, secs = {}, {}
-        for k in (5, 6):  # about 20 s of oracle work on 16 host threads
-            t = time.perf_counter()
-            got[k] = oracle.count(g, k, threads=th)
-            secs[k] = time.perf_counter() - t
-        n_all, dt = sum(got.values()), sum(secs.values())
-        line["cpu_baseline"] = {"value": n_all / dt, "unit": "k-cliques/s", "cores": th, "kind": "oracle",
-                                "sample": "full k=5 and k=6 counts of the same graph (" +
-                                          ", ".join(f"N_{k}={got[k]} in {secs[k]:.2f} s" for k in got) +
-                                          "); degeneracy-ordered vertex branch and bound, uint64"}
-        line["cpu_baseline"]["agrees_with_gpu"] = all(got[k] == counts[k] for k in got if k in counts)
-        log(f"cpu baseline {n_all / dt:.3e} k-cliques/s on {th} threads")
+    line["bench_wall_s"] = round(time.time() - T_START, 1)
     print(json.dumps(line), flush=True)
 
 

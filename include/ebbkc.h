@@ -254,7 +254,10 @@ ebbkc_status ebbkc_batch_create(ebbkc_graph *const *graphs, const int32_t *ks, i
 /* Run the batch and write the exact count of graph i to out_counts[i] (may be
  * NULL).  use_graph = 1 replays a HIP graph captured on the first call (the
  * counter reset, the per-class launches and the result copy); 0 launches the
- * same sequence directly.  Synchronises stream. */
+ * same sequence directly.  Synchronises stream.  A failure belongs to the
+ * graph that met it: a graph whose count reaches 2^64 gets 0 in out_counts
+ * and the call returns EBBKC_E_OVERFLOW, while every other graph's count is
+ * still written (out_counts is written in full whenever the launches ran). */
 ebbkc_status ebbkc_batch_run(ebbkc_batch *b, int32_t use_graph, uint64_t *out_counts, void *stream);
 
 /* Autotuner: times the batch under split thresholds {2^16, 2^22, 2^28, never}
@@ -306,7 +309,12 @@ ebbkc_status ebbkc_server_create(ebbkc_graph *const *graphs, int32_t n, const eb
                                  int64_t budget_bytes, ebbkc_server **out);
 /* Queue a request for the count of k-cliques (k >= 1) of catalogue graph
  * `graph`; *out_id identifies its result.  Never blocks on the device.
- * E_INVALID_ARG for a graph index outside the catalogue or k < 1. */
+ * E_INVALID_ARG for a graph index outside the catalogue or k < 1; E_K_RANGE
+ * for a k beyond the deepest search the library runs (2 + 2 * 136 + 4 = 278).
+ * Each request's result carries its own status: a request whose count
+ * reaches 2^64 reports EBBKC_E_OVERFLOW while the requests that shared its
+ * epoch keep their counts, and an epoch of several requests that cannot start
+ * (device memory, a runtime error) is retried one request per epoch. */
 ebbkc_status ebbkc_server_submit(ebbkc_server *s, int32_t graph, int32_t k, int64_t *out_id);
 /* Move up to max completed results to out (*n_out of them, in completion
  * order; the caller owns out, max entries); wait = 1 blocks until at least

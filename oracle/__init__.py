@@ -64,7 +64,6 @@ def _load():
             "orc_truss_sequential": [i32, vp, vp, vp, vp],
             "orc_degeneracy": [i32, vp, vp, vp, vp],
             "orc_count_vbb": [i32, vp, vp, i32, i32, i32, vp],
-            "orc_count_vbb_roots": [i32, vp, vp, i32, i32, i64, i64, vp],
             "orc_count_brute": [i32, vp, vp, i32, vp],
             "orc_list_lex": [i32, vp, vp, i32, i32, vp, u64, vp, vp, vp],
             "orc_seed_sizes": [i32, vp, vp, vp, vp],
@@ -139,15 +138,6 @@ def count(g, k: int, threads: int | None = None, shortcut: bool = True) -> int:
     out = ctypes.c_uint64()
     _chk(_load().orc_count_vbb(n, rp.ctypes.data, ci.ctypes.data, k, threads or default_threads(),
                                int(shortcut), ctypes.byref(out)), "count")
-    return int(out.value)
-
-
-def count_roots(g, k: int, r_begin: int, r_end: int, threads: int | None = None) -> int:
-    """k-cliques whose first vertex in the degeneracy order lies in positions [r_begin, r_end)."""
-    n, rp, ci = _csr(g)
-    out = ctypes.c_uint64()
-    _chk(_load().orc_count_vbb_roots(n, rp.ctypes.data, ci.ctypes.data, k, threads or default_threads(),
-                                     r_begin, r_end, ctypes.byref(out)), "count_roots")
     return int(out.value)
 
 

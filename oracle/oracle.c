@@ -594,14 +594,6 @@ int orc_count_vbb(int32_t n, const int32_t *rp, const int32_t *ci, int32_t k, in
     return vbb_run(n, rp, ci, k, nthreads, shortcut, 0, n, out);
 }
 
-/* The k-cliques whose first vertex in the degeneracy order is one of
- * order[r_begin..r_end): a bounded slice of the full count (k >= 3). */
-int orc_count_vbb_roots(int32_t n, const int32_t *rp, const int32_t *ci, int32_t k, int32_t nthreads,
-                        int64_t r_begin, int64_t r_end, uint64_t *out) {
-    if (k < 3 || nthreads < 1) return ORC_BAD_ARG;
-    return vbb_run(n, rp, ci, k, nthreads, 1, r_begin, r_end, out);
-}
-
 /* ----------------------------------------------------- brute force */
 
 /* Every k-subset of V (n <= 62), each tested on all of its pairs. */

@@ -14,6 +14,11 @@ constexpr int MAX_W = 4;              // widest bitmap class: 256 vertices
 constexpr int LIST_FUSED_K = 8;       // listings up to this k sort and hash tuples as they are written
 constexpr int LDS_FRAMES = 12;        // search frames kept in LDS (nodes with l >= 6)
 constexpr int GLOBAL_FRAMES = 124;    // further frames in device memory, per wave
+constexpr int LIST_LDS_FRAMES = 16;   // listing frames kept in LDS
+// a search at k needs device-memory frames past these k (count kernel,
+// listing kernel); a listing runs both kernels
+constexpr int SEARCH_DEEP_K = 2 + 2 * LDS_FRAMES + 4;
+constexpr int LIST_DEEP_K = 2 + 2 * LIST_LDS_FRAMES + 2;
 constexpr int MAX_K = 2 + 2 * (LDS_FRAMES + GLOBAL_FRAMES) + 4;
 
 // Graph arrays the build kernel reads.

@@ -238,7 +238,7 @@ ebbkc_status build_tasks(ebbkc_batch* b, hipStream_t s) {
     void* ptrs[] = {tasks, tg, keys, keys2, vals, vals2, hist, htmp};
     for (void* p : ptrs) dev_free(b, p, s);
     // frames for deep searches
-    if (b->kmax > 2 + 2 * LDS_FRAMES + 4) {
+    if (b->kmax > SEARCH_DEEP_K) {
         int64_t waves = 0;
         for (int W = 1; W <= MAX_W; ++W)
             waves = std::max(waves, search_grid_waves(W, false, total, b->cu_count, b->opt.blocks_per_cu));
@@ -302,26 +302,31 @@ ebbkc_status capture(ebbkc_batch* b, hipStream_t s) {
     return st;
 }
 
-ebbkc_status finish(ebbkc_batch* b, uint64_t* out) {
+// Results of the last run: the count of graph i into out[i] and, when
+// status is given, its own status into status[i] (an overflow or a depth
+// limit belongs to the graph that met it).  Returns the first failing status,
+// or EBBKC_OK.
+ebbkc_status finish(ebbkc_batch* b, uint64_t* out, ebbkc_status* status = nullptr) {
     const int n = (int)b->graphs.size();
     const int err = (int)b->h_ctr[6];
-    if (err & ERR_WIDTH) return EBBKC_E_WIDTH;
-    if (err & ERR_DEPTH) return EBBKC_E_K_RANGE;
-    ebbkc_status st = EBBKC_OK;
+    ebbkc_status first = EBBKC_OK;
     for (int i = 0; i < n; ++i) {
         const int k = b->ks[(size_t)i];
         ebbkc_graph* g = b->graphs[(size_t)i];
-        uint64_t v;
-        if (k == 1) v = (uint64_t)g->n;
+        uint64_t v = 0;
+        ebbkc_status st = EBBKC_OK;
+        if (err & ERR_WIDTH) st = EBBKC_E_WIDTH;
+        else if ((err & ERR_DEPTH) && k > SEARCH_DEEP_K) st = EBBKC_E_K_RANGE;
+        else if (k == 1) v = (uint64_t)g->n;
         else if (k == 2) v = (uint64_t)g->m;
         else if (k - 2 > g->tau) v = 0;
-        else {
-            if (b->h_tot[2 * i + 1] != 0 || (err & ERR_OVERFLOW)) st = EBBKC_E_OVERFLOW;
-            v = b->h_tot[2 * i];
-        }
-        if (out) out[i] = v;
+        else if (b->h_tot[2 * i + 1] != 0 || (err & ERR_OVERFLOW)) st = EBBKC_E_OVERFLOW;
+        else v = b->h_tot[2 * i];
+        if (out) out[i] = st ? 0 : v;
+        if (status) status[i] = st;
+        if (st && !first) first = st;
     }
-    return st;
+    return first;
 }
 
 std::mutex g_tune_mu;
@@ -581,6 +586,7 @@ struct ebbkc_server {
     struct Pending {
         ebbkc_result r;
         bool heavy;
+        bool solo;  // runs in an epoch of its own (after its shared epoch failed to start)
     };
     std::deque<Pending> pending;
     std::vector<ebbkc_result> done;
@@ -617,15 +623,16 @@ bool is_heavy(const ebbkc_server* S, int32_t graph, int32_t k) {
 // Finish the epoch of slot sl (its event has completed): results to done.
 void retire(ebbkc_server* S, ebbkc_server::Slot& sl) {
     std::vector<uint64_t> cnt(sl.reqs.size(), 0);
-    const ebbkc_status st = finish(sl.batch, cnt.data());
+    std::vector<ebbkc_status> sts(sl.reqs.size(), EBBKC_OK);
+    (void)finish(sl.batch, cnt.data(), sts.data());
     batch_destroy_impl(sl.batch);
     sl.batch = nullptr;
     const double t_done = S->now_ms();
     std::lock_guard<std::mutex> lk(S->mu);
     for (size_t i = 0; i < sl.reqs.size(); ++i) {
         ebbkc_result r = sl.reqs[i];
-        r.status = st;
-        r.count = st ? 0 : cnt[i];
+        r.status = sts[i];
+        r.count = sts[i] ? 0 : cnt[i];
         r.done_ms = t_done;
         S->done.push_back(r);
     }
@@ -657,6 +664,7 @@ void serve_loop(ebbkc_server* S) {
             ebbkc_server::Slot* slot;
             std::vector<ebbkc_result> reqs;
             int64_t bytes;
+            bool solo;
         };
         std::vector<Start> starts;
         {
@@ -667,15 +675,18 @@ void serve_loop(ebbkc_server* S) {
                 if (sl.batch) continue;
                 const bool light_only = si == SLOTS - 1;
                 bool heavy = light_only ? false : S->pending.front().heavy;
-                Start st{&sl, {}, 0};
+                Start st{&sl, {}, 0, false};
                 for (auto it = S->pending.begin(); it != S->pending.end() && (int)st.reqs.size() < SLOT_REQUESTS;) {
                     if (it->heavy != heavy) { ++it; continue; }
+                    if (it->solo && !st.reqs.empty()) break;
                     const int64_t need = request_bytes(S, it->r);
                     const bool alone = st.reqs.empty() && busy == 0 && starts.empty();
                     if (!alone && S->in_flight_bytes + st.bytes + need > S->budget) break;
                     st.bytes += need;
                     st.reqs.push_back(it->r);
+                    st.solo = it->solo;
                     it = S->pending.erase(it);
+                    if (st.solo) break;
                 }
                 if (st.reqs.empty()) continue;
                 S->in_flight += (int64_t)st.reqs.size();
@@ -712,22 +723,31 @@ void serve_loop(ebbkc_server* S) {
                                                 sl.h_ctr, &b);
             if (!st) st = enqueue(b, sl.stream);
             if (!st && hipEventRecord(sl.done, sl.stream) != hipSuccess) st = EBBKC_E_HIP;
-            if (st) {  // the epoch fails as a whole; its requests report the status
+            if (st) {
                 if (b) {
                     (void)hipStreamSynchronize(sl.stream);
                     batch_destroy_impl(b);
                 }
                 const double t_done = S->now_ms();
                 std::lock_guard<std::mutex> lk(S->mu);
-                for (auto& r : sl.reqs) {
-                    r.status = st;
-                    r.count = 0;
-                    r.done_ms = t_done;
-                    S->done.push_back(r);
+                if (sl.reqs.size() > 1) {
+                    // an epoch of several requests that could not start (device
+                    // memory, a runtime error) goes back to the front of the
+                    // queue one request per epoch, so a request that cannot
+                    // run fails alone and its neighbours still get results
+                    for (auto it = sl.reqs.rbegin(); it != sl.reqs.rend(); ++it)
+                        S->pending.push_front({*it, is_heavy(S, it->graph, it->k), true});
+                } else {
+                    for (auto& r : sl.reqs) {
+                        r.status = st;
+                        r.count = 0;
+                        r.done_ms = t_done;
+                        S->done.push_back(r);
+                    }
+                    S->epochs++;
                 }
                 S->in_flight -= (int64_t)sl.reqs.size();
                 S->in_flight_bytes -= sl.bytes;
-                S->epochs++;
                 sl.reqs.clear();
                 sl.bytes = 0;
                 S->done_cv.notify_all();
@@ -799,6 +819,7 @@ ebbkc_status ebbkc_server_create(ebbkc_graph* const* graphs, int32_t n, const eb
 
 ebbkc_status ebbkc_server_submit(ebbkc_server* S, int32_t graph, int32_t k, int64_t* out_id) {
     if (!S || graph < 0 || graph >= (int32_t)S->cat.size() || k < 1) return EBBKC_E_INVALID_ARG;
+    if (k > ebb::MAX_K) return EBBKC_E_K_RANGE;
     ebbkc_result r{};
     {
         std::lock_guard<std::mutex> lk(S->mu);
@@ -806,7 +827,7 @@ ebbkc_status ebbkc_server_submit(ebbkc_server* S, int32_t graph, int32_t k, int6
         r.graph = graph;
         r.k = k;
         r.arrival_ms = S->now_ms();
-        S->pending.push_back({r, ebb::is_heavy(S, graph, k)});
+        S->pending.push_back({r, ebb::is_heavy(S, graph, k), false});
     }
     S->cv.notify_one();
     if (out_id) *out_id = r.id;

@@ -699,7 +699,7 @@ ebbkc_status count_impl(ebbkc_graph* g, int32_t k, int64_t r_begin, int64_t r_en
 
     // ---- tasks (the scratch is sized for the worst case: every slot split)
     const int64_t Tmax = n * (int64_t)(64 * MAX_W);
-    const bool deep = k > 2 + 2 * LDS_FRAMES + 4;
+    const bool deep = k > SEARCH_DEEP_K;
     int64_t waves_max = 0;
     for (int W = 1; W <= MAX_W; ++W)
         waves_max = std::max(waves_max, search_grid_waves(W, false, Tmax, g->cu_count, g->opt.blocks_per_cu));
@@ -783,7 +783,9 @@ ebbkc_status list_impl(ebbkc_graph* g, int32_t k, int64_t r_begin, int64_t r_end
             CHKH(hipMemcpyAsync(&T, toff + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
             CHKH(hipStreamSynchronize(s));
             if (T > 0) {
-                const bool deep = k > 2 + 2 * 16 + 2;
+                // pass 1 runs the count kernel, pass 2 the listing kernel: frames
+                // in device memory when either needs them
+                const bool deep = k > std::min(SEARCH_DEEP_K, LIST_DEEP_K);
                 const int64_t waves = list_grid_waves(MAX_W, T, g->cu_count);
                 const int64_t wsearch = search_grid_waves(MAX_W, false, T, g->cu_count, g->opt.blocks_per_cu);
                 const size_t fbytes = deep ? (size_t)std::max(waves, wsearch) * GLOBAL_FRAMES *
@@ -901,7 +903,7 @@ ebbkc_status count_seeds_impl(ebbkc_graph* g, int32_t k, const int64_t* eids, in
     int64_t T = 0;
     for (int W = 0; W < MAX_W; ++W) { ccount[W] = tasks[W].size(); T += (int64_t)tasks[W].size(); }
     if (T) {
-        const bool deep = k > 2 + 2 * LDS_FRAMES + 4;
+        const bool deep = k > SEARCH_DEEP_K;
         const size_t fbytes =
             deep ? (size_t)search_grid_waves(MAX_W, false, T, g->cu_count, g->opt.blocks_per_cu) * GLOBAL_FRAMES *
                        search_frame_bytes(MAX_W)

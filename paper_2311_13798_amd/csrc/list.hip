@@ -23,7 +23,6 @@ struct LFrame {
     int32_t x, l, y, pad;
 };
 
-constexpr int LIST_LDS_FRAMES = 16;
 
 template <int N>
 __device__ __forceinline__ void sort_net(int32_t (&v)[N]) {

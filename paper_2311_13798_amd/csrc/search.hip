@@ -959,7 +959,12 @@ __global__ __launch_bounds__(256, (W <= 2 ? 4 : (W <= 3 ? 3 : 2))) void k_search
 
         }
     task_done:
-        if (tacc.ovf && lane == 0) atomicOr(a.err, ERR_OVERFLOW);
+        // a batch flags an overflow on its own graph only (top bit of the
+        // graph's high word), so co-scheduled graphs keep their results
+        if (tacc.ovf && lane == 0) {
+            if (a.graph_total) atomicOr(&a.graph_total[2 * gi + 1], 1ull << 63);
+            else atomicOr(a.err, ERR_OVERFLOW);
+        }
         if (a.per_task && lane == 0) a.per_task[it] = tacc.lo();
         if (a.graph_total) {
             if (lane == 0 && tacc.lo()) {

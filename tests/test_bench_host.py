@@ -1,5 +1,5 @@
 """Host-side pieces of the measurement (no GPU): bench.py refuses more than one GPU before touching
-one, and the counter record is built from rocprofv3's per-dispatch CSV rows by the copy-kernel
+one, its step plan keeps the run inside the wall budget, and the counter record is built from rocprofv3's per-dispatch CSV rows by the copy-kernel
 calibration (bytes = counter KiB x 1024 x the copy's true bytes / its counter bytes)."""
 import csv
 import json
@@ -30,7 +30,7 @@ def _write_counters(d, counter, rows):
 
 def test_traffic_record_from_counter_rows(tmp_path):
     sys.path.insert(0, ROOT)
-    from paper_2311_13798_amd import traffic_probe as tp
+    import bench as tp
     mul = "void at::native::vectorized_elementwise_kernel<4, at::native::AUnaryFunctor<float, float, float, " \
           "at::native::binary_internal::MulFunctor<float> > >(int)"
     fill = "void at::native::vectorized_elementwise_kernel<4, at::native::FillFunctor<float> >(int)"
@@ -39,10 +39,36 @@ def test_traffic_record_from_counter_rows(tmp_path):
     _write_counters(str(tmp_path / "f"), "FETCH_SIZE", [(fill, 10.0), (mul, 524288.0), (search, 1000.0)])
     _write_counters(str(tmp_path / "w"), "WRITE_SIZE", [(fill, 1048576.0), (mul, 1048576.0), (search, 300.0)])
     out = str(tmp_path / "rec.json")
-    rec = tp.write_record(str(tmp_path / "f"), str(tmp_path / "w"), out, 9, "cmd")
+    rec = tp.traffic_record(str(tmp_path / "f"), str(tmp_path / "w"), out, 9, "cmd")
     assert rec == json.load(open(out))
     assert rec["source_sha256"] == tp.source_sha256()
     assert rec["copy_kernel"]["fetch_scale"] == 2.0 and rec["copy_kernel"]["write_scale"] == 1.0
     e = rec["launches"]["ebb::k_search<3, false>@k=9"]
     assert (e["fetch_KiB"], e["write_KiB"]) == (1000.0, 300.0)
     assert e["hbm_bytes"] == 1000 * 1024 * 2 + 300 * 1024
+
+
+def test_step_plan_keeps_the_wall_budget():
+    sys.path.insert(0, ROOT)
+    import bench
+    # the first warmup and the first timed step always run
+    assert bench.plan_warmups(5, 0, 0.0, -10.0, 20)
+    assert bench.plan_timed(0, 20, 85.0, -10.0)
+    # a second warmup only while all requested timed steps still fit after it
+    assert not bench.plan_warmups(5, 1, 85.0, 200.0, 20)
+    assert bench.plan_warmups(5, 1, 10.0, 250.0, 20)
+    assert not bench.plan_warmups(1, 1, 1.0, 1e9, 20)
+    # a timed step starts only while it is expected to end before the deadline
+    assert bench.plan_timed(1, 20, 85.0, 86.0)
+    assert not bench.plan_timed(1, 20, 85.0, 84.0)
+    assert not bench.plan_timed(20, 20, 1.0, 1e9)
+    # simulated driver command (--steps 20 --warmup 5) with 85 s steps after 90 s of start-up:
+    # the measurement ends by the 300 s deadline plus at most one step
+    t, warm, timed = 90.0, 0, 0
+    while bench.plan_warmups(5, warm, 85.0 if warm else 0.0, 300.0 - t, 20):
+        t += 85.0
+        warm += 1
+    while bench.plan_timed(timed, 20, 85.0, 300.0 - t):
+        t += 85.0
+        timed += 1
+    assert (warm, timed) == (1, 1) and t <= 300.0 + 85.0

@@ -1,7 +1,9 @@
 """The headline workload at full size (R-MAT scale 18, edge factor 16, seed 1) against stored oracle
-values (tests/golden/rmat18.json, written by tests/golden/make_golden.py from the oracle alone):
-per-edge arrays by SHA-256, counts at k = 1..7 bit-exact, and per-seed counts at k = 5, 7, 9 on 300
-sampled seeds each (the oracle computes those one by one; the full k = 9 count is beyond it)."""
+values (tests/golden/*.json, written by tests/golden/make_golden.py from the oracle alone):
+per-edge arrays by SHA-256, counts at k = 1..8 bit-exact, per-seed counts at k = 5, 7, 9 on 300
+sampled seeds each, and at k = 8 and 9 on sampled seeds whose sub-branch has 129..192 vertices
+(the three-word bitmap class, whose launch dominates the k = 8 and k = 9 counts; the oracle computes
+seeds one by one, the full k = 9 count is beyond it)."""
 import hashlib
 import json
 import os
@@ -47,6 +49,32 @@ def test_counts(setup):
     for k, v in fx["counts"].items():
         print(f"case rmat18 count k={k}", flush=True)
         assert G.count(int(k)) == v, k
+
+
+def test_count_k8(setup):
+    ebb, fx, g, G = setup
+    path = os.path.join(os.path.dirname(__file__), "golden", "rmat18_k8.json")
+    if not os.path.exists(path):
+        pytest.skip("the oracle's 8-clique count of this graph has not been written yet")
+    ref = json.load(open(path))
+    assert ref["sha256"] == fx["sha256"] and ref["k"] == 8
+    print("case rmat18 count k=8", flush=True)
+    assert G.count(8) == ref["count"]
+
+
+@pytest.mark.parametrize("k", [8, 9])
+def test_sampled_seed_counts_three_word_class(setup, k):
+    ebb, fx, g, G = setup
+    ref = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "rmat18_w3seeds.json")))
+    assert ref["sha256"] == fx["sha256"] and ref["rank_sha256"] == fx["rank_sha256"]
+    rec = ref["seed_samples"][str(k)]
+    sub = G.export(ebb.ARR_SUBSIZE)
+    eids = np.array(rec["eids"], dtype=np.int64)
+    assert len(eids) >= 30 and ((sub[eids] > 128) & (sub[eids] <= 192)).all()
+    out = np.zeros(len(eids), np.uint64)
+    print(f"case rmat18 w3 seeds k={k}", flush=True)
+    ebb.ebbkc_count_seeds(G.handle, k, eids, out)
+    assert [int(x) for x in out] == [int(x) for x in rec["counts"]]
 
 
 @pytest.mark.parametrize("k", [5, 7, 9])

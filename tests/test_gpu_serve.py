@@ -1,9 +1,14 @@
-"""Served form: every request's count equals the standalone count of the same (graph, k), whatever
-requests shared its epoch; a small budget forces many epochs, a large one merges requests."""
+"""Served form: every request's count equals the oracle's count and the standalone count of the same
+(graph, k), whatever requests shared its epoch; a small budget forces many epochs, a large one merges
+requests; a request that overflows or asks for an impossible k fails alone."""
+import json
+import os
+
 import numpy as np
 import pytest
 
 import graphgen
+import oracle
 from graphgen import configs
 
 pytestmark = pytest.mark.gpu
@@ -18,6 +23,8 @@ def catalogue():
           graphgen.cocktail_party(10), configs.cl_planted(10000, nplant=2), graphgen.empty(5)]
     Gs = [ebb.Graph.from_csr(g) for g in gs]
     alone = {(i, k): G.count(k) for i, G in enumerate(Gs) for k in range(1, 13)}
+    want = {(i, k): oracle.count(g, k) for i, g in enumerate(gs) for k in range(1, 13)}
+    assert alone == want
     yield ebb, Gs, alone
     for G in Gs:
         G.close()
@@ -59,18 +66,24 @@ def test_burst_then_drain(catalogue):
 
 def test_light_requests_run_beside_a_heavy_one():
     # R-MAT scale 13 at k = 12 takes ~2.3 s alone; requests arriving while it runs start in other
-    # epoch slots and finish long before it, each with its standalone count
+    # epoch slots and finish long before it, each with its standalone count, which is the oracle's
+    # (R-MAT s13 from the stored oracle values, the light graphs counted by the oracle here)
     import time
 
     import torch
     import paper_2311_13798_amd as ebb
     from paper_2311_13798_amd.serve import Server
     torch.cuda.set_device(0)
-    heavy = ebb.Graph.from_csr(configs.rmat_scale(13))
-    lights = [ebb.Graph.from_csr(g) for g in (configs.er_small(), graphgen.rmat(10, 16, seed=1),
-                                              graphgen.er_planted(300, 0.05, 1, 25, 25, 2))]
+    fx = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "served.json")))["graphs"]["rmat13"]
+    g13 = configs.rmat_scale(13)
+    assert g13.sha256() == fx["sha256"]
+    heavy = ebb.Graph.from_csr(g13)
+    lgs = (configs.er_small(), graphgen.rmat(10, 16, seed=1), graphgen.er_planted(300, 0.05, 1, 25, 25, 2))
+    lights = [ebb.Graph.from_csr(g) for g in lgs]
     want_heavy = heavy.count(12)
+    assert want_heavy == fx["counts"]["12"]
     alone = {(i, k): G.count(k) for i, G in enumerate(lights) for k in range(3, 8)}
+    assert alone == {(i, k): oracle.count(g, k) for i, g in enumerate(lgs) for k in range(3, 8)}
     S = Server([heavy] + lights, 1 << 40)
     hid = S.submit(0, 12)
     time.sleep(0.05)
@@ -91,3 +104,52 @@ def test_light_requests_run_beside_a_heavy_one():
     assert before >= 40, before
     for G in [heavy] + lights:
         G.close()
+
+
+def test_a_failing_request_fails_alone(catalogue):
+    # K_70 at k = 34, 35 has C(70, k) > 2^64 cliques: those requests report EBBKC_E_OVERFLOW while the
+    # requests that shared their epoch keep their counts; a k beyond the deepest search the library
+    # supports is refused at submission.  Two long requests (R-MAT s13, k = 12) hold both slots that
+    # take heavy requests, so the K_70 requests queue up and start together in one epoch.
+    import time
+    from math import comb
+
+    import torch
+    from paper_2311_13798_amd.serve import Server
+    ebb, Gs, alone = catalogue
+    torch.cuda.set_device(0)
+    fx = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "served.json")))["graphs"]["rmat13"]
+    K70 = ebb.Graph.from_csr(graphgen.complete(70))
+    R13 = ebb.Graph.from_csr(configs.rmat_scale(13))
+    cat = [K70, R13] + Gs
+    S = Server(cat, 1 << 40)
+    with pytest.raises(ebb.EbbkcError) as ei:
+        S.submit(2, 100000)
+    assert ei.value.status == ebb.E_K_RANGE
+    blockers = []
+    for _ in range(2):
+        blockers.append(S.submit(1, 12))
+        time.sleep(0.1)
+    heavy = [(0, 35), (0, 20), (0, 34), (0, 25), (0, 10)]
+    rng = np.random.default_rng(9)
+    pairs = heavy + [(2 + int(rng.integers(0, len(Gs))), int(rng.integers(3, 10))) for _ in range(30)]
+    ids = [S.submit(g, k) for g, k in pairs]
+    got = {}
+    while len(got) < len(ids) + len(blockers):
+        for r in S.poll(wait=True):
+            got[r["id"]] = r
+    S.close()
+    for b in blockers:
+        assert got[b]["status"] == 0 and got[b]["count"] == fx["counts"]["12"]
+    admits = {got[i]["admit_ms"] for i, (g, _) in zip(ids, pairs) if g == 0}
+    assert len(admits) == 1  # the K_70 requests ran in one epoch
+    for i, (g, k) in zip(ids, pairs):
+        r = got[i]
+        if g == 0 and k in (34, 35):
+            assert r["status"] == ebb.E_OVERFLOW and r["count"] == 0
+        elif g == 0:
+            assert r["status"] == 0 and r["count"] == comb(70, k)
+        else:
+            assert r["status"] == 0 and r["count"] == alone[(g - 2, k)], (g, k)
+    K70.close()
+    R13.close()
