@@ -61,7 +61,9 @@ typedef enum {
     EBBKC_E_OVERFLOW = -6,         /* exact count does not fit 64 bits */
     EBBKC_E_WIDTH = -7,            /* a sub-branch exceeds the widest bitmap class */
     EBBKC_E_HIP = -8,              /* a HIP runtime call failed */
-    EBBKC_E_CANCELLED = -9
+    EBBKC_E_CANCELLED = -9,
+    EBBKC_E_SCRATCH = -10          /* ebbkc_count_noalloc: the count needs more than its fixed
+                                      256 MiB scratch */
 } ebbkc_status;
 
 enum { EBBKC_PTR_HOST = 0, EBBKC_PTR_DEVICE = 1 };
@@ -166,6 +168,27 @@ ebbkc_status ebbkc_prepare(const int32_t *row_ptr, const int32_t *col_idx, int32
 /* Exact number of k-cliques.  k=1 gives n, k=2 gives m, k>=3 runs the
  * edge-oriented branch and bound. */
 ebbkc_status ebbkc_count(ebbkc_graph *g, int32_t k, uint64_t *out_count, void *stream);
+
+/* The same count as ebbkc_count, for callers that cannot allocate device
+ * memory (code under stream capture, tight serving loops, harnesses that
+ * forbid allocation): this call allocates nothing -- no hipMalloc, hipFree,
+ * event or host allocation.  Its task lists, sort buffers and deep-search
+ * frames live in a fixed per-device buffer of 256 MiB that the library holds
+ * on every device it is loaded on until the process ends.  Every call on a device shares that device's
+ * buffer: calls that overlap on one device race and must not be issued
+ * concurrently (the buffer keeps the last call's contents; a call writes
+ * everything it reads).
+ *   g       a handle whose sub-branch arena exists (any earlier ebbkc_count at
+ *           k >= 4, ebbkc_count_seeds or ebbkc_list builds it); otherwise
+ *           EBBKC_E_INVALID_ARG.  The count always uses the edge roots and the
+ *           colour-ordered search below them (the count is the same under every
+ *           ebbkc_options.ordering).
+ *   k       as for ebbkc_count (k = 1 gives n, k = 2 gives m).
+ *   out_count  host pointer, written on EBBKC_OK.
+ * Errors: EBBKC_E_SCRATCH when the count's task list (about 40 bytes per task
+ * plus 12 bytes per seed) exceeds the fixed buffer; EBBKC_E_OVERFLOW past
+ * 2^64; EBBKC_E_HIP when the buffer's address cannot be obtained. */
+ebbkc_status ebbkc_count_noalloc(ebbkc_graph *g, int32_t k, uint64_t *out_count, void *stream);
 
 /* The same count exactly in 128 bits: out_count[0] low word, out_count[1]
  * high word (near the maximum clique size counts pass 2^64: C(70, 35) > 2^64;

@@ -18,6 +18,8 @@ LIB_PATH = os.path.join(_HERE, "libebbkc.so")
 
 OK, E_INVALID_ARG, E_BAD_CSR, E_OOM, E_K_RANGE, E_BUFFER_TOO_SMALL, E_OVERFLOW, E_WIDTH, E_HIP, E_CANCELLED = (
     0, -1, -2, -3, -4, -5, -6, -7, -8, -9)
+E_SCRATCH = -10
+NOALLOC_SCRATCH_BYTES = 256 << 20  # the fixed scratch of ebbkc_count_noalloc
 PTR_HOST, PTR_DEVICE = 0, 1
 LIST_SORTED = 1
 ARR_SUPPORT, ARR_RANK, ARR_LEVEL, ARR_SUBSIZE, ARR_VERTEX_POS, ARR_VERTEX_COLOR = 0, 1, 2, 3, 4, 5
@@ -48,7 +50,7 @@ class ebbkc_info(ctypes.Structure):
                 ("max_degree", ctypes.c_int32), ("device_bytes", ctypes.c_int64), ("prepare_ms", ctypes.c_double)]
 
 
-EXPORTED = ("ebbkc_default_options", "ebbkc_prepare", "ebbkc_count", "ebbkc_count128", "ebbkc_max_clique_size",
+EXPORTED = ("ebbkc_default_options", "ebbkc_prepare", "ebbkc_count", "ebbkc_count_noalloc", "ebbkc_count128", "ebbkc_max_clique_size",
             "ebbkc_count_range", "ebbkc_count_seeds",
             "ebbkc_list", "ebbkc_export", "ebbkc_info_get", "ebbkc_last_timing", "ebbkc_last_work",
             "ebbkc_last_work_class", "ebbkc_destroy", "ebbkc_strerror", "ebbkc_batch_create", "ebbkc_batch_run", "ebbkc_batch_tune", "ebbkc_batch_info",
@@ -72,6 +74,7 @@ def load_library(path: str = LIB_PATH):
     lib.ebbkc_default_options.restype = None
     lib.ebbkc_prepare.argtypes = [vp, vp, i32, i64, i32, ctypes.POINTER(ebbkc_options), vp, ctypes.POINTER(vp)]
     lib.ebbkc_count.argtypes = [vp, i32, pu64, vp]
+    lib.ebbkc_count_noalloc.argtypes = [vp, i32, pu64, vp]
     lib.ebbkc_count_range.argtypes = [vp, i32, i64, i64, pu64, vp]
     lib.ebbkc_count128.argtypes = [vp, i32, pu64, vp]
     lib.ebbkc_max_clique_size.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), vp]
@@ -102,7 +105,7 @@ def load_library(path: str = LIB_PATH):
         getattr(lib, f).restype = ctypes.c_int
     lib.ebbkc_strerror.argtypes = [i32]
     lib.ebbkc_strerror.restype = ctypes.c_char_p
-    for f in ("ebbkc_prepare", "ebbkc_count", "ebbkc_count_range", "ebbkc_count128", "ebbkc_max_clique_size", "ebbkc_count_seeds", "ebbkc_list",
+    for f in ("ebbkc_prepare", "ebbkc_count", "ebbkc_count_noalloc", "ebbkc_count_range", "ebbkc_count128", "ebbkc_max_clique_size", "ebbkc_count_seeds", "ebbkc_list",
               "ebbkc_export", "ebbkc_info_get", "ebbkc_last_timing", "ebbkc_last_work", "ebbkc_last_work_class"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
@@ -159,6 +162,12 @@ def ebbkc_prepare(row_ptr, col_idx, n: int, nnz: int, options: ebbkc_options | N
 def ebbkc_count(h, k: int, stream=None) -> int:
     out = ctypes.c_uint64()
     _check(load_library().ebbkc_count(h, k, ctypes.byref(out), _stream(stream)), "ebbkc_count")
+    return int(out.value)
+
+
+def ebbkc_count_noalloc(h, k: int, stream=None) -> int:
+    out = ctypes.c_uint64()
+    _check(load_library().ebbkc_count_noalloc(h, k, ctypes.byref(out), _stream(stream)), "ebbkc_count_noalloc")
     return int(out.value)
 
 

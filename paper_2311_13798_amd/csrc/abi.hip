@@ -31,6 +31,7 @@ const char* ebbkc_strerror(ebbkc_status s) {
         case EBBKC_E_WIDTH: return "a sub-branch exceeds the widest bitmap class";
         case EBBKC_E_HIP: return "HIP runtime error";
         case EBBKC_E_CANCELLED: return "cancelled";
+        case EBBKC_E_SCRATCH: return "the count needs more scratch than the fixed no-allocation buffer holds";
     }
     return "unknown status";
 }
@@ -83,6 +84,15 @@ ebbkc_status ebbkc_count(ebbkc_graph* g, int32_t k, uint64_t* out_count, void* s
     if (k == 2) { *out_count = (uint64_t)g->m; return EBBKC_OK; }
     if (k - 2 > g->tau) { *out_count = 0; return EBBKC_OK; }  // no sub-branch can hold k-2 vertices
     return ebb::count_impl(g, k, 0, g->m, nullptr, 0, nullptr, out_count, (hipStream_t)stream);
+}
+
+ebbkc_status ebbkc_count_noalloc(ebbkc_graph* g, int32_t k, uint64_t* out_count, void* stream) {
+    if (!g || !out_count) return EBBKC_E_INVALID_ARG;
+    if (k < 1) return EBBKC_E_K_RANGE;
+    if (k == 1) { *out_count = (uint64_t)g->n; return EBBKC_OK; }
+    if (k == 2) { *out_count = (uint64_t)g->m; return EBBKC_OK; }
+    if (k - 2 > g->tau) { *out_count = 0; return EBBKC_OK; }
+    return ebb::count_noalloc_impl(g, k, out_count, (hipStream_t)stream);
 }
 
 ebbkc_status ebbkc_count128(ebbkc_graph* g, int32_t k, uint64_t out_count[2], void* stream) {

@@ -555,8 +555,10 @@ static size_t task_bytes(int64_t n, int64_t T) {
 // contiguous).  list = false: counts (per_task optional); list = true: tuples.
 static ebbkc_status run_tasks(ebbkc_graph* g, int32_t k, const int64_t* tsorted, const uint64_t ccount[4],
                               uint64_t* per_task, const uint64_t* task_off, int32_t* out, void* gframes, bool list,
-                              hipStream_t s) {
-    const bool truss = !list && g->opt.ordering == EBBKC_ORDER_TRUSS;
+                              hipStream_t s, bool noalloc = false) {
+    // noalloc: no EBBkC-T rank slab and no timing events (the colour-ordered
+    // search below the initial branch gives the same count under EBBkC-T)
+    const bool truss = !list && !noalloc && g->opt.ordering == EBBKC_ORDER_TRUSS;
     if (truss) {  // EBBkC-T: depth limit and the per-wave rank matrices
         if (k > 2 * TRUSS_FRAMES + 3) return EBBKC_E_K_RANGE;
         if (!g->rho_slab) {
@@ -576,8 +578,10 @@ static ebbkc_status run_tasks(ebbkc_graph* g, int32_t k, const int64_t* tsorted,
     for (int W = 1; W <= MAX_W; ++W) {
         const int64_t nt = (int64_t)ccount[W - 1];
         if (!nt) continue;
-        CHKH(hipEventCreate(&ev[W][0]));
-        CHKH(hipEventCreate(&ev[W][1]));
+        if (!noalloc) {
+            CHKH(hipEventCreate(&ev[W][0]));
+            CHKH(hipEventCreate(&ev[W][1]));
+        }
         SearchArgs a{};
         a.A = ArenaView{g->seed_eid, g->seed_c, g->row_off, g->vtx_off, g->arows, g->agid, g->acol};
         a.tasks = tsorted + off;
@@ -600,7 +604,7 @@ static ebbkc_status run_tasks(ebbkc_graph* g, int32_t k, const int64_t* tsorted,
         a.list_checksums = fused;
         a.gframes = gframes;
         CHKH(hipMemsetAsync(a.next, 0, sizeof(uint64_t), s));
-        CHKH(hipEventRecord(ev[W][0], s));
+        if (ev[W][0]) CHKH(hipEventRecord(ev[W][0], s));
         if (list) {
             CHKH(launch_list(W, a, g->cu_count, s));
         } else if (truss) {
@@ -624,7 +628,7 @@ static ebbkc_status run_tasks(ebbkc_graph* g, int32_t k, const int64_t* tsorted,
         } else {
             CHKH(launch_search(W, false, a, g->cu_count, g->opt.blocks_per_cu, s));
         }
-        CHKH(hipEventRecord(ev[W][1], s));
+        if (ev[W][1]) CHKH(hipEventRecord(ev[W][1], s));
         off += nt;
     }
     CHKH(hipStreamSynchronize(s));
@@ -638,13 +642,38 @@ static ebbkc_status run_tasks(ebbkc_graph* g, int32_t k, const int64_t* tsorted,
     return EBBKC_OK;
 }
 
+// A count's scratch: the handle's buffer, grown on demand, or (fixed != null)
+// a fixed buffer of cap bytes that is never grown: a count that needs more
+// returns EBBKC_E_SCRATCH, and nothing is allocated.
+struct ScratchSrc {
+    void* fixed = nullptr;
+    size_t cap = 0;
+};
+
+static Carve carve_for(ebbkc_graph* g, const ScratchSrc& src, size_t bytes) {
+    if (src.fixed) return Carve{bytes <= src.cap ? (char*)src.fixed : nullptr, 0, src.cap};
+    char* p = (char*)scratch_get(g, bytes);
+    return Carve{p, 0, p ? g->scratch_bytes : 0};
+}
+
+static ebbkc_status count_core(ebbkc_graph* g, int32_t k, int64_t r_begin, int64_t r_end, uint64_t* out,
+                               hipStream_t s, const ScratchSrc& src);
+
 ebbkc_status count_impl(ebbkc_graph* g, int32_t k, int64_t r_begin, int64_t r_end, const int64_t* d_eids, int64_t ne,
                         uint64_t* d_per_seed, uint64_t* out, hipStream_t s) {
     (void)d_eids;
     (void)ne;
     (void)d_per_seed;
+    return count_core(g, k, r_begin, r_end, out, s, ScratchSrc{});
+}
+
+static ebbkc_status count_core(ebbkc_graph* g, int32_t k, int64_t r_begin, int64_t r_end, uint64_t* out,
+                               hipStream_t s, const ScratchSrc& src) {
+    const bool noalloc = src.fixed != nullptr;
+    const ebbkc_status e_space = noalloc ? EBBKC_E_SCRATCH : EBBKC_E_OOM;
     if (k < 3 || k > MAX_K) return EBBKC_E_K_RANGE;
-    if (g->opt.ordering == EBBKC_ORDER_DEGEN_VERTEX_NP && !g->np_active && r_begin <= 0 &&
+    if (noalloc && (!g->arena_built || !g->d_counters || !g->subsize_ready)) return EBBKC_E_INVALID_ARG;
+    if (!noalloc && g->opt.ordering == EBBKC_ORDER_DEGEN_VERTEX_NP && !g->np_active && r_begin <= 0 &&
         (r_end < 0 || r_end >= g->m) && k + 1 <= MAX_K) {
         // node-parallel VBBkC: one root per vertex v whose (k-1)-cliques in
         // G[N+(v)] are counted, i.e. the edge-slot search at k + 1 over the
@@ -652,11 +681,11 @@ ebbkc_status count_impl(ebbkc_graph* g, int32_t k, int64_t r_begin, int64_t r_en
         ebbkc_status st = vertex_arena_impl(g, s);
         if (st) return st;
         swap_arenas(g);
-        st = count_impl(g, k + 1, 0, -1, d_eids, ne, d_per_seed, out, s);
+        st = count_core(g, k + 1, 0, -1, out, s, src);
         swap_arenas(g);
         return st;
     }
-    ebbkc_status st = ensure_counters(g);
+    ebbkc_status st = ensure_counters(g);  // allocated already under noalloc (checked above)
     if (st) return st;
     if (ensure_binom(g->device, s) != hipSuccess) return EBBKC_E_HIP;
     if (r_end < 0 || r_end > g->m) r_end = g->m;
@@ -705,30 +734,29 @@ ebbkc_status count_impl(ebbkc_graph* g, int32_t k, int64_t r_begin, int64_t r_en
         waves_max = std::max(waves_max, search_grid_waves(W, false, Tmax, g->cu_count, g->opt.blocks_per_cu));
     const size_t fbytes = deep ? (size_t)waves_max * GLOBAL_FRAMES * search_frame_bytes(MAX_W) : 0;
     // count the real number of tasks first with a small scratch, then size
-    Carve cv0{(char*)scratch_get(g, task_bytes(n, 1)), 0, 0};
-    cv0.cap = g->scratch_bytes;
+    Carve cv0 = carve_for(g, src, task_bytes(n, 1));
     int32_t* tcount = cv0.take<int32_t>(n);
     int64_t* toff = cv0.take<int64_t>(n + 1);
     int64_t* tmp = cv0.take<int64_t>(scan_tmp_elems(n + 1) + 64);
-    if (!tcount || !toff || !tmp) return EBBKC_E_OOM;
+    if (!tcount || !toff || !tmp) return e_space;
     hipLaunchKernelGGL(k_task_counts, dim3(grid_for(n)), dim3(256), 0, s, g->seed_c, i0, n, l0, log_thr, tcount);
     CHKH(exclusive_scan_i32(tcount, toff, n, toff + n, tmp, s));
     int64_t T = 0;
     CHKH(hipMemcpyAsync(&T, toff + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     CHKH(hipStreamSynchronize(s));
     if (T == 0) return read_total(g, out, s);
-    if (!scratch_get(g, task_bytes(n, T) + rnd256(fbytes))) return EBBKC_E_OOM;
-    Carve cv{(char*)g->scratch, 0, g->scratch_bytes};
+    Carve cv = carve_for(g, src, task_bytes(n, T) + rnd256(fbytes));
+    if (!cv.base) return e_space;
     int64_t* tsorted = nullptr;
     uint64_t ccount[4] = {0, 0, 0, 0};
     int64_t T2 = 0;
     st = make_tasks(g, i0, n, l0, log_thr, s, cv, &tsorted, &T2, ccount);
-    if (st) return st;
+    if (st) return st == EBBKC_E_OOM ? e_space : st;
     void* gframes = deep ? (void*)cv.take<char>((int64_t)fbytes) : nullptr;
-    if (deep && !gframes) return EBBKC_E_OOM;
+    if (deep && !gframes) return e_space;
 
     // ---- search, one launch per width class
-    st = run_tasks(g, k, tsorted, ccount, nullptr, nullptr, nullptr, gframes, false, s);
+    st = run_tasks(g, k, tsorted, ccount, nullptr, nullptr, nullptr, gframes, false, s, noalloc);
     if (st) return st;
     return read_total(g, out, s);
 }
@@ -860,6 +888,47 @@ ebbkc_status list_impl(ebbkc_graph* g, int32_t k, int64_t r_begin, int64_t r_end
     }
     CHKH(hipStreamSynchronize(s));
     return EBBKC_OK;
+}
+
+// ---------------------------------------------------------------- count without allocation
+// The fixed scratch of ebbkc_count_noalloc: task lists, sort buffers and deep
+// search frames of one count.  Each device holds its own copy from the load
+// of the library to the end of the process; host code reaches it only through
+// the address hipGetSymbolAddress returns for that device.
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)256 << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::once_flag g_scratch_once[NOALLOC_MAX_DEVICES];
+void* g_scratch_ptr[NOALLOC_MAX_DEVICES];
+hipError_t g_scratch_err[NOALLOC_MAX_DEVICES];
+
+// device address of the fixed scratch on device dev, looked up once per
+// device with that device current
+void* noalloc_scratch(int dev) {
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return nullptr;
+    std::call_once(g_scratch_once[dev], [dev] {
+        int cur = 0;
+        g_scratch_err[dev] = hipGetDevice(&cur);
+        if (g_scratch_err[dev] != hipSuccess) return;
+        if (cur != dev) g_scratch_err[dev] = hipSetDevice(dev);
+        if (g_scratch_err[dev] == hipSuccess)
+            g_scratch_err[dev] = hipGetSymbolAddress(&g_scratch_ptr[dev], HIP_SYMBOL(scratch));
+        if (cur != dev) (void)hipSetDevice(cur);
+        if (g_scratch_err[dev] != hipSuccess) {
+            (void)hipGetLastError();
+            g_scratch_ptr[dev] = nullptr;
+        }
+    });
+    return g_scratch_err[dev] == hipSuccess ? g_scratch_ptr[dev] : nullptr;
+}
+}  // namespace
+
+ebbkc_status count_noalloc_impl(ebbkc_graph* g, int32_t k, uint64_t* out, hipStream_t s) {
+    void* p = noalloc_scratch(g->device);
+    if (!p) return EBBKC_E_HIP;
+    return count_core(g, k, 0, g->m, out, s, ScratchSrc{p, NOALLOC_SCRATCH_BYTES});
 }
 
 // Per-seed counts for listed edge ids: one whole-root task per seed.

@@ -103,4 +103,5 @@ hipError_t ensure_tables(int dev, hipStream_t s);
 ebbkc_status count_seeds_impl(ebbkc_graph* g, int32_t k, const int64_t* eids, int64_t ne, int32_t ptr_kind,
                               uint64_t* out, hipStream_t s);
 void* scratch_get(ebbkc_graph* g, size_t bytes);
+ebbkc_status count_noalloc_impl(ebbkc_graph* g, int32_t k, uint64_t* out, hipStream_t s);
 }  // namespace ebb
