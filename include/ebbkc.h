@@ -61,7 +61,7 @@ typedef enum {
     EBBKC_E_OVERFLOW = -6,         /* exact count does not fit 64 bits */
     EBBKC_E_WIDTH = -7,            /* a sub-branch exceeds the widest bitmap class */
     EBBKC_E_HIP = -8,              /* a HIP runtime call failed */
-    EBBKC_E_CANCELLED = -9,
+    EBBKC_E_CANCELLED = -9,        /* a served request withdrawn by ebbkc_server_cancel */
     EBBKC_E_SCRATCH = -10          /* ebbkc_count_noalloc: the count needs more than its fixed
                                       256 MiB scratch */
 } ebbkc_status;
@@ -73,10 +73,14 @@ enum { EBBKC_PTR_HOST = 0, EBBKC_PTR_DEVICE = 1 };
 typedef struct {
     int32_t early_termination; /* 1 (default): clique / 2-plex closed forms (Section 5) */
     int32_t t_plex;            /* largest t whose t-plexes (every vertex misses at most t-1
-                                  others) are counted in closed form: 1 cliques, 2 also 2-plexes
-                                  (Algorithm kC2Plex), 3 also 3-plexes (Algorithm kCtPlex, whose
-                                  missing pairs form paths and cycles); 0 (default) the rule of
-                                  Section 6.1: 2 when k <= tau/2, else 3 */
+                                  others) end the branching early (Section 5): 1 cliques, 2 also
+                                  2-plexes (Algorithm kC2Plex, closed form), 3 also 3-plexes
+                                  (their missing pairs form paths and cycles: closed form), 4..16
+                                  also t-plexes by Algorithm kCtPlex (branching on the inverse
+                                  graph, the vertices adjacent to all others in closed form; for
+                                  counts of at most 96 vertices); 0 (default) the rule of Section
+                                  6.1: 2 when k <= tau/2, else 3.  Other values: E_INVALID_ARG
+                                  from ebbkc_prepare.  Listings branch beyond t = 2. */
     int32_t rule1;             /* 1 (default): colour pruning Rule (1), Section 4.3 */
     int32_t rule2;             /* 1 (default): colour pruning Rule (2), Section 4.3 */
     int32_t waves_per_block;   /* workgroup size in wavefronts (default 4) */
@@ -114,8 +118,27 @@ typedef struct {
                                     per-seed counts, listings and batches under it use the edge
                                     roots of DEGEN_VERTEX (same results).
                                   Other values: EBBKC_E_INVALID_ARG. */
-    int32_t reserved[5];
+    int32_t batch_build;       /* batches (ebbkc_batch_create): where each task's sub-branch comes
+                                  from.  EBBKC_BATCH_ARENA (1): every graph's sub-branch arena is
+                                  built in device memory once and tasks load their g_i from it;
+                                  EBBKC_BATCH_BUILD (2): no arena, every task builds its g_i in
+                                  LDS from the graph's arrays (memory O(m) per graph, for batches
+                                  whose arenas would not fit); 0 (default): arenas when every
+                                  graph already has one or their total size is at most half the
+                                  free device memory, else build.  Counts are the same. */
+    int32_t node_split;        /* runtime splitting of search nodes over waves through a device
+                                  queue (root sub-branches and their subtrees are independent,
+                                  Section 6.2 (7)): 0 (default): a node with l >= 4 and at least
+                                  2^16 l-subsets is handed to a waiting wave while some wave waits
+                                  for work; n >= 2: the same with n l-subsets; 1: every node with
+                                  l >= 4 is handed over while the queue has room (exercises the
+                                  queue at every depth); -1: off.  Not used by listings, per-seed
+                                  counts, EBBkC-T or non-persistent launches (blocks_per_cu = -1).
+                                  Counts are the same. */
+    int32_t reserved[3];
 } ebbkc_options;
+
+enum { EBBKC_BATCH_AUTO = 0, EBBKC_BATCH_ARENA = 1, EBBKC_BATCH_BUILD = 2 };
 
 enum {
     EBBKC_ORDER_HYBRID = 0,
@@ -165,8 +188,14 @@ ebbkc_status ebbkc_prepare(const int32_t *row_ptr, const int32_t *col_idx, int32
                            int32_t ptr_kind, const ebbkc_options *opt, void *stream,
                            ebbkc_graph **out);
 
-/* Exact number of k-cliques.  k=1 gives n, k=2 gives m, k>=3 runs the
- * edge-oriented branch and bound. */
+/* Exact number of k-cliques: the k-vertex subsets of V whose vertices are
+ * pairwise adjacent (the k-clique listing problem, Section 2).  k=1 gives n,
+ * k=2 gives m (the l = 1 and l = 2 terminations of Algorithm EBBkC); k>=3
+ * runs the edge-oriented branch and bound (Eq. edge-oriented-branching,
+ * Section 4.1, every k-clique counted once under its first edge in pi_tau).
+ * out_count: host pointer, written on EBBKC_OK.  Errors: EBBKC_E_K_RANGE for
+ * k < 1 or k beyond the deepest search (278); EBBKC_E_OVERFLOW when the count
+ * reaches 2^64 (ebbkc_count128 gives it); EBBKC_E_OOM / EBBKC_E_HIP. */
 ebbkc_status ebbkc_count(ebbkc_graph *g, int32_t k, uint64_t *out_count, void *stream);
 
 /* The same count as ebbkc_count, for callers that cannot allocate device
@@ -214,7 +243,10 @@ ebbkc_status ebbkc_count_range(ebbkc_graph *g, int32_t k, int64_t r_begin, int64
 ebbkc_status ebbkc_count_seeds(ebbkc_graph *g, int32_t k, const int64_t *eids, int64_t ne,
                                int32_t ptr_kind, uint64_t *out, void *stream);
 
-/* Write every k-cliques (k >= 1) whose seed rank is in [r_begin, r_end) to
+/* The k-cliques themselves (the listing of Section 2's problem; Algorithm
+ * EBBkC outputs S plus each vertex (l = 1) or edge (l = 2) of the last
+ * sub-branch, Algorithm kC2Plex the combinations of a 2-plex).
+ * Write every k-clique (k >= 1) whose seed rank is in [r_begin, r_end) to
  * d_buf (device memory, cap tuples of k int32, row-major), each tuple in
  * ascending vertex order.  With EBBKC_LIST_SORTED the tuples are sorted
  * lexicographically.  *out_written is the number of tuples; if it exceeds
@@ -247,12 +279,15 @@ ebbkc_status ebbkc_last_timing(const ebbkc_graph *g, double out_ms[4]);
  * prepared with ebbkc_options.count_work = 1 (otherwise zeros):
  * [0] seeds whose sub-branch was built, [1] search nodes evaluated,
  * [2] 64-bit word operations on candidate bitmaps (one AND + popcount of
- * one word each), [3] reserved. */
+ * one word each), [3] search nodes handed to another wave through the split
+ * queue (node_split). */
 ebbkc_status ebbkc_last_work(const ebbkc_graph *g, uint64_t out[4]);
 
 /* The same counters for the launch of one bitmap width class
  * (width_class = W in 1..4: sub-branches of at most 64*W vertices), so that
- * a launch's work can be set against its time from ebbkc_last_timing.
+ * a launch's work can be set against its time from ebbkc_last_timing; out[3]
+ * is that launch's wave-finish tail in nanoseconds (its last wave's end minus
+ * the mean end of its waves).
  * E_INVALID_ARG for a class outside 1..4. */
 ebbkc_status ebbkc_last_work_class(const ebbkc_graph *g, int32_t width_class, uint64_t out[4]);
 
@@ -339,6 +374,12 @@ ebbkc_status ebbkc_server_create(ebbkc_graph *const *graphs, int32_t n, const eb
  * epoch keep their counts, and an epoch of several requests that cannot start
  * (device memory, a runtime error) is retried one request per epoch. */
 ebbkc_status ebbkc_server_submit(ebbkc_server *s, int32_t graph, int32_t k, int64_t *out_id);
+/* Withdraw request id.  A request still waiting is removed at once and its
+ * result (status EBBKC_E_CANCELLED, count 0) is available to poll; a request
+ * whose epoch is already running finishes with that epoch but reports
+ * EBBKC_E_CANCELLED.  E_INVALID_ARG for an unknown id or one whose result is
+ * already available. */
+ebbkc_status ebbkc_server_cancel(ebbkc_server *s, int64_t id);
 /* Move up to max completed results to out (*n_out of them, in completion
  * order; the caller owns out, max entries); wait = 1 blocks until at least
  * one is available or nothing is pending.  A failed request is a result with

@@ -24,6 +24,7 @@ PTR_HOST, PTR_DEVICE = 0, 1
 LIST_SORTED = 1
 ARR_SUPPORT, ARR_RANK, ARR_LEVEL, ARR_SUBSIZE, ARR_VERTEX_POS, ARR_VERTEX_COLOR = 0, 1, 2, 3, 4, 5
 ORDER_HYBRID, ORDER_COLOR, ORDER_DEGEN_VERTEX, ORDER_TRUSS, ORDER_DEGEN_VERTEX_NP = 0, 1, 2, 3, 4
+BATCH_AUTO, BATCH_ARENA, BATCH_BUILD = 0, 1, 2
 
 
 class EbbkcError(RuntimeError):
@@ -36,7 +37,8 @@ class ebbkc_options(ctypes.Structure):
     _fields_ = [("early_termination", ctypes.c_int32), ("t_plex", ctypes.c_int32), ("rule1", ctypes.c_int32),
                 ("rule2", ctypes.c_int32), ("waves_per_block", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
                 ("split_threshold", ctypes.c_int32), ("count_work", ctypes.c_int32),
-                ("dense_k4", ctypes.c_int32), ("ordering", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+                ("dense_k4", ctypes.c_int32), ("ordering", ctypes.c_int32), ("batch_build", ctypes.c_int32),
+                ("node_split", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
 
 class ebbkc_result(ctypes.Structure):
@@ -54,7 +56,7 @@ EXPORTED = ("ebbkc_default_options", "ebbkc_prepare", "ebbkc_count", "ebbkc_coun
             "ebbkc_count_range", "ebbkc_count_seeds",
             "ebbkc_list", "ebbkc_export", "ebbkc_info_get", "ebbkc_last_timing", "ebbkc_last_work",
             "ebbkc_last_work_class", "ebbkc_destroy", "ebbkc_strerror", "ebbkc_batch_create", "ebbkc_batch_run", "ebbkc_batch_tune", "ebbkc_batch_info",
-            "ebbkc_batch_destroy", "ebbkc_server_create", "ebbkc_server_submit", "ebbkc_server_poll",
+            "ebbkc_batch_destroy", "ebbkc_server_create", "ebbkc_server_submit", "ebbkc_server_cancel", "ebbkc_server_poll",
             "ebbkc_server_stats", "ebbkc_server_destroy")
 
 _lib = None
@@ -97,11 +99,13 @@ def load_library(path: str = LIB_PATH):
         getattr(lib, f).restype = ctypes.c_int
     lib.ebbkc_server_create.argtypes = [vp, i32, ctypes.POINTER(ebbkc_options), i64, ctypes.POINTER(vp)]
     lib.ebbkc_server_submit.argtypes = [vp, i32, i32, ctypes.POINTER(ctypes.c_int64)]
+    lib.ebbkc_server_cancel.argtypes = [vp, i64]
     lib.ebbkc_server_poll.argtypes = [vp, ctypes.POINTER(ebbkc_result), i32, i32, ctypes.POINTER(ctypes.c_int32)]
     lib.ebbkc_server_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
     lib.ebbkc_server_destroy.argtypes = [vp]
     lib.ebbkc_server_destroy.restype = None
-    for f in ("ebbkc_server_create", "ebbkc_server_submit", "ebbkc_server_poll", "ebbkc_server_stats"):
+    for f in ("ebbkc_server_create", "ebbkc_server_submit", "ebbkc_server_cancel", "ebbkc_server_poll",
+              "ebbkc_server_stats"):
         getattr(lib, f).restype = ctypes.c_int
     lib.ebbkc_strerror.argtypes = [i32]
     lib.ebbkc_strerror.restype = ctypes.c_char_p
@@ -329,6 +333,10 @@ def ebbkc_server_submit(s, graph: int, k: int) -> int:
     rid = ctypes.c_int64()
     _check(load_library().ebbkc_server_submit(s, graph, k, ctypes.byref(rid)), "ebbkc_server_submit")
     return int(rid.value)
+
+
+def ebbkc_server_cancel(s, rid: int):
+    _check(load_library().ebbkc_server_cancel(s, rid), "ebbkc_server_cancel")
 
 
 def ebbkc_server_poll(s, max_results: int = 4096, wait: bool = False):

@@ -65,7 +65,9 @@ ebbkc_status ebbkc_prepare(const int32_t* row_ptr, const int32_t* col_idx, int32
     if (hipGetDeviceProperties(&prop, g->device) != hipSuccess) { delete g; return EBBKC_E_HIP; }
     g->cu_count = prop.multiProcessorCount;
     if (opt) g->opt = *opt; else ebbkc_default_options(&g->opt);
-    if (g->opt.ordering < EBBKC_ORDER_HYBRID || g->opt.ordering > EBBKC_ORDER_DEGEN_VERTEX_NP) {
+    if (g->opt.ordering < EBBKC_ORDER_HYBRID || g->opt.ordering > EBBKC_ORDER_DEGEN_VERTEX_NP ||
+        g->opt.batch_build < EBBKC_BATCH_AUTO || g->opt.batch_build > EBBKC_BATCH_BUILD || g->opt.node_split < -1 ||
+        g->opt.t_plex < 0 || g->opt.t_plex > 16) {
         delete g;
         return EBBKC_E_INVALID_ARG;
     }

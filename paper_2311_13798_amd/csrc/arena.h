@@ -7,7 +7,7 @@
 
 namespace ebb {
 
-enum : int { ERR_WIDTH = 1, ERR_OVERFLOW = 2, ERR_DEPTH = 4, ERR_CAP = 8 };
+enum : int { ERR_WIDTH = 1, ERR_OVERFLOW = 2, ERR_DEPTH = 4, ERR_CAP = 8, ERR_QUEUE = 16 };
 enum : int { OPT_ET = 1, OPT_RULE1 = 4, OPT_RULE2 = 8, OPT_WORK = 16 };
 
 constexpr int MAX_W = 4;              // widest bitmap class: 256 vertices
@@ -106,6 +106,32 @@ __device__ inline int root_tasks(int c, int l0, double log_threshold, F&& emit) 
     return n;
 }
 
+// Runtime splitting: a search node handed from one wave to any idle wave
+// through a device queue (root sub-branches and their subtrees are
+// independent, Section 6.2 (7)).  The item names the task it came from
+// (which gives the slot, graph and k), the node's candidate set and l.
+struct SplitItem {
+    int64_t it;
+    uint64_t P[MAX_W];
+    int32_t l;
+    int32_t ready;  // 1 once the item is written (release store)
+};
+// queue counters: [SQ_HEAD] items claimed, [SQ_RESERVE] items reserved,
+// [SQ_BUSY] waves working (a wave counts itself when it starts), [SQ_IDLE]
+// waves waiting for items, [SQ_PUSHED] items pushed over the launch
+enum : int { SQ_HEAD = 0, SQ_RESERVE = 1, SQ_BUSY = 2, SQ_IDLE = 3, SQ_PUSHED = 4, SQ_WORDS = 8 };
+constexpr int64_t SQ_CAP = 1 << 16;        // items per launch
+constexpr int64_t SQ_SLACK = 1 << 13;       // more than the waves of one launch
+constexpr int SPLIT_OFF = 0, SPLIT_ON_DEMAND = 1, SPLIT_FORCED = 2;
+
+// A graph whose sub-branches are built by the search tasks themselves (no
+// arena): its arrays, |V(g_i)| of every edge, and the colours of G kept in
+// every g_i under EBBkC-C (null: each g_i coloured on its own).
+struct BuildGraph {
+    GraphView G;
+    const int32_t* subsize;
+    const int32_t* vcol;
+};
 struct SearchArgs {
     ArenaView A;
     const int64_t* tasks;
@@ -137,6 +163,21 @@ struct SearchArgs {
     const int32_t* graph_k;
     const int32_t* graph_tau;
     unsigned long long* graph_total;
+    // batches whose tasks build their own sub-branch (the search kernel's
+    // build variant): graph g's arrays; a task's slot is its seed edge id
+    const BuildGraph* bviews;
+    // runtime splitting (squeue null: off).  SPLIT_ON_DEMAND: a node with
+    // l >= 4 whose bound C(|P|, l) reaches split_bound is pushed while waves
+    // wait for work and fewer items are pending than waves wait; SPLIT_FORCED:
+    // every such node is pushed while the queue has room (a test of the
+    // queue at every depth)
+    SplitItem* squeue;
+    unsigned long long* sq;      // SQ_WORDS counters, zeroed before the launch
+    int32_t split_mode;
+    uint64_t split_bound;
+    // when counting work: [sum of wave end times, latest end, waves, ~earliest
+    // start] in 10 ns ticks of the constant-rate clock
+    unsigned long long* wave_time;
 };
 
 // EBBkC-T search (one launch per width class): the fields mean what they mean
@@ -165,10 +206,11 @@ struct TrussArgs {
 hipError_t launch_build(int W, const BuildArgs& a, int cus, hipStream_t s);
 hipError_t launch_search_truss(int W, const TrussArgs& a, int cus, hipStream_t s);
 size_t truss_slab_bytes(int cus);
-hipError_t launch_search(int W, bool list, const SearchArgs& a, int cus, int blocks_per_cu, hipStream_t s);
-int64_t search_grid_waves(int W, bool list, int64_t ntasks, int cus, int blocks_per_cu);
+hipError_t launch_search(int W, bool build, const SearchArgs& a, int cus, int blocks_per_cu, hipStream_t s);
+int64_t search_grid_waves(int W, bool build, int64_t ntasks, int cus, int blocks_per_cu);
 size_t search_frame_bytes(int W);
 hipError_t launch_binom_init(hipStream_t s);
+hipError_t launch_sq_reset(unsigned long long* sq, SplitItem* items, hipStream_t s);
 float k4_weight_of(int32_t dense_k4);
 hipError_t launch_list(int W, const SearchArgs& a, int cus, hipStream_t s);
 size_t list_frame_bytes(int W);

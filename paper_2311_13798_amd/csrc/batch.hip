@@ -21,6 +21,7 @@
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <set>
 #include <string>
 #include <vector>
 
@@ -35,6 +36,10 @@ struct ebbkc_batch {
     std::vector<int32_t> ks;
     ebbkc_options opt{};
     int cu_count = 256;
+    // sub-branches: loaded from every graph's arena, or built by each task in
+    // LDS from the graph's arrays (bviews)
+    bool build = false;
+    ebb::BuildGraph* bviews = nullptr;
     // device
     ebb::ArenaView* views = nullptr;
     int32_t* gk = nullptr;
@@ -43,6 +48,8 @@ struct ebbkc_batch {
     int32_t* tgraph = nullptr;
     unsigned long long* gtot = nullptr;  // 2 per graph
     unsigned long long* ctr = nullptr;   // [0..4) class work counters, [4..6) unused, [6] err, [8..11] work
+    ebb::SplitItem* squeue = nullptr;    // runtime split queue (null: off)
+    unsigned long long* sq = nullptr;
     void* gframes = nullptr;
     int64_t ntasks = 0;
     uint64_t ccount[4] = {0, 0, 0, 0};
@@ -134,6 +141,28 @@ __global__ void k_bclear(unsigned long long* __restrict__ a, int64_t na, unsigne
     }
 }
 
+// bytes of the arena slots of graph g (|V(g_i)| >= 1): c W words of rows plus
+// 6 bytes of id and colour per vertex; and the widest sub-branch
+__global__ void k_arena_bytes(const int32_t* __restrict__ subsize, int64_t m, unsigned long long* __restrict__ out) {
+    uint64_t b = 0;
+    int mx = 0;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (int64_t)gridDim.x * blockDim.x) {
+        const int c = subsize[e];
+        if (c > 0) b += (uint64_t)c * (uint64_t)width_of(c) * 8 + 6 * (uint64_t)c;
+        mx = c > mx ? c : mx;
+    }
+    b = wave_sum(b);
+    mx = wave_max(mx);
+    if (lane_id() == 0) {
+        if (b) atomicAdd(&out[0], (unsigned long long)b);
+        atomicMax(&out[1], (unsigned long long)mx);
+    }
+}
+
+GraphView graph_arrays(const ebbkc_graph* g) {
+    return GraphView{g->rp, g->ci, g->erank, g->rrow, g->orp, g->orow, g->eu, g->ev, g->rank};
+}
+
 int opts_of(const ebbkc_options& o) {
     int f = 0;
     if (o.early_termination) f |= OPT_ET;
@@ -171,8 +200,11 @@ ebbkc_status build_tasks(ebbkc_batch* b, hipStream_t s) {
     // per graph: task counts and offsets (scratch sized for the largest graph)
     std::vector<int64_t> gbase((size_t)n + 1, 0);
     std::vector<int64_t*> toffs((size_t)n, nullptr);
+    // seeds: arena slots, or (build mode) every edge with its |V(g_i)|
+    auto seeds_of = [&](const ebbkc_graph* g) -> int64_t { return b->build ? g->m : g->nseeds; };
+    auto sizes_of = [&](const ebbkc_graph* g) -> const int32_t* { return b->build ? g->subsize : g->seed_c; };
     int64_t total = 0, nsmax = 0;
-    for (int i = 0; i < n; ++i) nsmax = std::max(nsmax, b->graphs[(size_t)i]->nseeds);
+    for (int i = 0; i < n; ++i) nsmax = std::max(nsmax, seeds_of(b->graphs[(size_t)i]));
     int32_t* tc = nullptr;
     int64_t* tmp = nullptr;
     CHKB(dev_alloc(b, (void**)&tc, sizeof(int32_t) * (nsmax + 1), s));
@@ -181,11 +213,11 @@ ebbkc_status build_tasks(ebbkc_batch* b, hipStream_t s) {
     for (int i = 0; i < n; ++i) {
         ebbkc_graph* g = b->graphs[(size_t)i];
         const int k = b->ks[(size_t)i];
-        if (k < 3 || g->nseeds == 0) continue;
-        const int64_t ns = g->nseeds;
+        if (k < 3 || seeds_of(g) == 0) continue;
+        const int64_t ns = seeds_of(g);
         int64_t* to = nullptr;
         CHKB(dev_alloc(b, (void**)&to, sizeof(int64_t) * (ns + 1), s));
-        hipLaunchKernelGGL(k_btask_counts, dim3(gridn(ns)), dim3(256), 0, s, g->seed_c, ns, k - 2, log_thr, tc);
+        hipLaunchKernelGGL(k_btask_counts, dim3(gridn(ns)), dim3(256), 0, s, sizes_of(g), ns, k - 2, log_thr, tc);
         CHKB(exclusive_scan_i32(tc, to, ns, to + ns, tmp, s));
         CHKB(hipMemcpyAsync(&tcount[(size_t)i], to + ns, sizeof(int64_t), hipMemcpyDeviceToHost, s));
         toffs[(size_t)i] = to;
@@ -220,7 +252,7 @@ ebbkc_status build_tasks(ebbkc_batch* b, hipStream_t s) {
     for (int i = 0; i < n; ++i) {
         if (!toffs[(size_t)i]) continue;
         ebbkc_graph* g = b->graphs[(size_t)i];
-        hipLaunchKernelGGL(k_btask_fill, dim3(gridn(g->nseeds)), dim3(256), 0, s, g->seed_c, g->nseeds,
+        hipLaunchKernelGGL(k_btask_fill, dim3(gridn(seeds_of(g))), dim3(256), 0, s, sizes_of(g), seeds_of(g),
                            b->ks[(size_t)i] - 2, log_thr, toffs[(size_t)i], gbase[(size_t)i], (int32_t)i, tasks, tg,
                            keys, vals);
     }
@@ -241,7 +273,7 @@ ebbkc_status build_tasks(ebbkc_batch* b, hipStream_t s) {
     if (b->kmax > SEARCH_DEEP_K) {
         int64_t waves = 0;
         for (int W = 1; W <= MAX_W; ++W)
-            waves = std::max(waves, search_grid_waves(W, false, total, b->cu_count, b->opt.blocks_per_cu));
+            waves = std::max(waves, search_grid_waves(W, b->build, total, b->cu_count, b->opt.blocks_per_cu));
         CHKB(dev_alloc(b, &b->gframes, (size_t)waves * GLOBAL_FRAMES * search_frame_bytes(MAX_W), s));
     }
     b->dirty = true;
@@ -263,7 +295,8 @@ ebbkc_status enqueue(ebbkc_batch* b, hipStream_t s) {
         a.tasks = b->tasks + off;
         a.task_graph = b->tgraph + off;
         a.ntasks = nt;
-        a.views = b->views;
+        a.views = b->build ? nullptr : b->views;
+        a.bviews = b->build ? b->bviews : nullptr;
         a.graph_k = b->gk;
         a.graph_total = b->gtot;
         a.opts = opts_of(b->opt);
@@ -275,7 +308,14 @@ ebbkc_status enqueue(ebbkc_batch* b, hipStream_t s) {
         a.work = b->ctr + 8;
         a.err = (int*)(b->ctr + 6);
         a.gframes = b->gframes;
-        CHKB(launch_search(W, false, a, b->cu_count, b->opt.blocks_per_cu, s));
+        if (b->squeue && b->opt.node_split != -1 && b->opt.blocks_per_cu != -1) {  // persistent grids only
+            a.squeue = b->squeue;
+            a.sq = b->sq;
+            a.split_mode = b->opt.node_split == 1 ? SPLIT_FORCED : SPLIT_ON_DEMAND;
+            a.split_bound = b->opt.node_split == 1 ? 0 : (b->opt.node_split >= 2 ? (uint64_t)b->opt.node_split : 1ull << 16);
+            CHKB(launch_sq_reset(b->sq, b->squeue, s));
+        }
+        CHKB(launch_search(W, b->build, a, b->cu_count, b->opt.blocks_per_cu, s));
         off += nt;
     }
     CHKB(hipMemcpyAsync(b->h_tot, b->gtot, sizeof(unsigned long long) * 2 * n, hipMemcpyDeviceToHost, s));
@@ -316,6 +356,7 @@ ebbkc_status finish(ebbkc_batch* b, uint64_t* out, ebbkc_status* status = nullpt
         uint64_t v = 0;
         ebbkc_status st = EBBKC_OK;
         if (err & ERR_WIDTH) st = EBBKC_E_WIDTH;
+        else if (err & ERR_QUEUE) st = EBBKC_E_HIP;
         else if ((err & ERR_DEPTH) && k > SEARCH_DEEP_K) st = EBBKC_E_K_RANGE;
         else if (k == 1) v = (uint64_t)g->n;
         else if (k == 2) v = (uint64_t)g->m;
@@ -378,7 +419,7 @@ void batch_destroy_impl(ebbkc_batch* b) {
     free_tasks(b);
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
-    void* ptrs[] = {b->views, b->gk, b->gtau, b->gtot, b->ctr};
+    void* ptrs[] = {b->views, b->bviews, b->gk, b->gtau, b->gtot, b->ctr, b->squeue, b->sq};
     for (void* p : ptrs) dev_free(b, p, b->mem_stream);
     if (b->own_host) {
         if (b->h_tot) (void)hipHostFree(b->h_tot);
@@ -407,15 +448,58 @@ ebbkc_status batch_create_impl(ebbkc_graph* const* graphs, const int32_t* ks, in
         return EBBKC_E_HIP;
     }
     std::vector<ArenaView> views((size_t)n);
+    std::vector<BuildGraph> bviews((size_t)n);
+    bool all_arenas = true;
     for (int i = 0; i < n; ++i) {
         ebbkc_graph* g = graphs[i];
         if (!g || g->device != b->device || ks[i] < 1 || ks[i] > MAX_K) { delete b; return EBBKC_E_INVALID_ARG; }
         b->kmax = std::max(b->kmax, ks[i]);
+        if (ks[i] >= 3 && ks[i] - 2 <= g->tau && !g->arena_built) all_arenas = false;
+    }
+    // where the sub-branches come from: arenas, or built by each task in LDS
+    // (auto: arenas when they exist already or fit half the free memory)
+    int mode = b->opt.batch_build;
+    if (mode == EBBKC_BATCH_AUTO && all_arenas) mode = EBBKC_BATCH_ARENA;
+    if (mode != EBBKC_BATCH_ARENA) {
+        unsigned long long* est = nullptr;
+        if (hipMalloc((void**)&est, sizeof(unsigned long long) * 2 * n) != hipSuccess) { delete b; return EBBKC_E_OOM; }
+        (void)hipMemsetAsync(est, 0, sizeof(unsigned long long) * 2 * n, s);
+        for (int i = 0; i < n; ++i) {
+            ebbkc_graph* g = graphs[i];
+            if (ks[i] < 3 || ks[i] - 2 > g->tau) continue;
+            ebbkc_status st = subsize_impl(g, s);
+            if (st) { (void)hipFree(est); delete b; return st; }
+            if (g->m) hipLaunchKernelGGL(k_arena_bytes, dim3(gridn(g->m)), dim3(256), 0, s, g->subsize, g->m, est + 2 * i);
+        }
+        std::vector<unsigned long long> h((size_t)2 * n);
+        const bool ok = hipMemcpyAsync(h.data(), est, sizeof(unsigned long long) * 2 * n, hipMemcpyDeviceToHost, s) ==
+                            hipSuccess && hipStreamSynchronize(s) == hipSuccess;
+        (void)hipFree(est);
+        if (!ok) { delete b; return EBBKC_E_HIP; }
+        uint64_t need = 0, widest = 0;
+        for (int i = 0; i < n; ++i) {
+            if (!graphs[i]->arena_built) need += h[(size_t)2 * i];
+            widest = std::max<uint64_t>(widest, h[(size_t)2 * i + 1]);
+        }
+        if (mode == EBBKC_BATCH_AUTO) {
+            size_t fr = 0, tot = 0;
+            if (hipMemGetInfo(&fr, &tot) != hipSuccess) { delete b; return EBBKC_E_HIP; }
+            mode = need <= fr / 2 ? EBBKC_BATCH_ARENA : EBBKC_BATCH_BUILD;
+        }
+        if (mode == EBBKC_BATCH_BUILD && widest > (uint64_t)(64 * MAX_W)) { delete b; return EBBKC_E_WIDTH; }
+    }
+    b->build = mode == EBBKC_BATCH_BUILD;
+    for (int i = 0; i < n; ++i) {
+        ebbkc_graph* g = graphs[i];
         if (ks[i] >= 3 && ks[i] - 2 <= g->tau) {
-            ebbkc_status st = arena_impl(g, s);
-            if (st) { delete b; return st; }
+            if (!b->build) {
+                ebbkc_status st = arena_impl(g, s);
+                if (st) { delete b; return st; }
+            }
         }
         views[(size_t)i] = ArenaView{g->seed_eid, g->seed_c, g->row_off, g->vtx_off, g->arows, g->agid, g->acol};
+        bviews[(size_t)i] = BuildGraph{graph_arrays(g), g->subsize,
+                                       g->opt.ordering == EBBKC_ORDER_COLOR ? g->vcol : nullptr};
     }
     // graphs whose k exceeds tau + 2 or is below 3 contribute no task
     std::vector<int32_t> kk(b->ks);
@@ -424,10 +508,16 @@ ebbkc_status batch_create_impl(ebbkc_graph* const* graphs, const int32_t* ks, in
     b->ks = kk;
     auto fail = [&](ebbkc_status st) { batch_destroy_impl(b); return st; };
     if (dev_alloc(b, (void**)&b->views, sizeof(ArenaView) * n, s) != hipSuccess) return fail(EBBKC_E_OOM);
+    if (b->build && dev_alloc(b, (void**)&b->bviews, sizeof(BuildGraph) * n, s) != hipSuccess) return fail(EBBKC_E_OOM);
     if (dev_alloc(b, (void**)&b->gk, sizeof(int32_t) * n, s) != hipSuccess) return fail(EBBKC_E_OOM);
     if (dev_alloc(b, (void**)&b->gtau, sizeof(int32_t) * n, s) != hipSuccess) return fail(EBBKC_E_OOM);
     if (dev_alloc(b, (void**)&b->gtot, sizeof(unsigned long long) * 2 * n, s) != hipSuccess) return fail(EBBKC_E_OOM);
     if (dev_alloc(b, (void**)&b->ctr, sizeof(unsigned long long) * 16, s) != hipSuccess) return fail(EBBKC_E_OOM);
+    if (b->opt.node_split != -1 && b->opt.blocks_per_cu != -1) {
+        if (dev_alloc(b, (void**)&b->squeue, sizeof(SplitItem) * SQ_CAP, s) != hipSuccess ||
+            dev_alloc(b, (void**)&b->sq, sizeof(unsigned long long) * SQ_WORDS, s) != hipSuccess)
+            return fail(EBBKC_E_OOM);
+    }
     if (h_tot && h_ctr) {
         b->own_host = false;
         b->h_tot = h_tot;
@@ -440,7 +530,9 @@ ebbkc_status batch_create_impl(ebbkc_graph* const* graphs, const int32_t* ks, in
     }
     std::vector<int32_t> taus((size_t)n);
     for (int i = 0; i < n; ++i) taus[(size_t)i] = graphs[i]->tau;
-    if (hipMemcpyAsync(b->views, views.data(), sizeof(ArenaView) * n, hipMemcpyHostToDevice, s) != hipSuccess ||
+    if ((b->build && hipMemcpyAsync(b->bviews, bviews.data(), sizeof(BuildGraph) * n, hipMemcpyHostToDevice, s) !=
+                         hipSuccess) ||
+        hipMemcpyAsync(b->views, views.data(), sizeof(ArenaView) * n, hipMemcpyHostToDevice, s) != hipSuccess ||
         hipMemcpyAsync(b->gk, b->ks.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s) != hipSuccess ||
         hipMemcpyAsync(b->gtau, taus.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s) != hipSuccess)
         return fail(EBBKC_E_HIP);
@@ -590,6 +682,8 @@ struct ebbkc_server {
     };
     std::deque<Pending> pending;
     std::vector<ebbkc_result> done;
+    std::vector<int64_t> cancelled;  // ids of running requests whose result is withdrawn
+    std::set<int64_t> running;       // ids admitted to an epoch and not yet retired (under mu)
     std::vector<std::vector<int64_t>> chist;  // per graph: seeds by |V(g_i)| (0..256)
     int64_t next_id = 0, in_flight = 0, epochs = 0, max_epoch_requests = 0, in_flight_bytes = 0;
     std::chrono::steady_clock::time_point t0;
@@ -632,7 +726,13 @@ void retire(ebbkc_server* S, ebbkc_server::Slot& sl) {
     for (size_t i = 0; i < sl.reqs.size(); ++i) {
         ebbkc_result r = sl.reqs[i];
         r.status = sts[i];
-        r.count = sts[i] ? 0 : cnt[i];
+        S->running.erase(r.id);
+        auto ci = std::find(S->cancelled.begin(), S->cancelled.end(), r.id);
+        if (ci != S->cancelled.end()) {
+            S->cancelled.erase(ci);
+            r.status = EBBKC_E_CANCELLED;
+        }
+        r.count = r.status ? 0 : cnt[i];
         r.done_ms = t_done;
         S->done.push_back(r);
     }
@@ -684,6 +784,7 @@ void serve_loop(ebbkc_server* S) {
                     if (!alone && S->in_flight_bytes + st.bytes + need > S->budget) break;
                     st.bytes += need;
                     st.reqs.push_back(it->r);
+                    S->running.insert(it->r.id);
                     st.solo = it->solo;
                     it = S->pending.erase(it);
                     if (st.solo) break;
@@ -730,6 +831,7 @@ void serve_loop(ebbkc_server* S) {
                 }
                 const double t_done = S->now_ms();
                 std::lock_guard<std::mutex> lk(S->mu);
+                for (auto& r : sl.reqs) S->running.erase(r.id);
                 if (sl.reqs.size() > 1) {
                     // an epoch of several requests that could not start (device
                     // memory, a runtime error) goes back to the front of the
@@ -739,6 +841,8 @@ void serve_loop(ebbkc_server* S) {
                         S->pending.push_front({*it, is_heavy(S, it->graph, it->k), true});
                 } else {
                     for (auto& r : sl.reqs) {
+                        auto ci = std::find(S->cancelled.begin(), S->cancelled.end(), r.id);
+                        if (ci != S->cancelled.end()) S->cancelled.erase(ci);
                         r.status = st;
                         r.count = 0;
                         r.done_ms = t_done;
@@ -832,6 +936,31 @@ ebbkc_status ebbkc_server_submit(ebbkc_server* S, int32_t graph, int32_t k, int6
     S->cv.notify_one();
     if (out_id) *out_id = r.id;
     return EBBKC_OK;
+}
+
+ebbkc_status ebbkc_server_cancel(ebbkc_server* S, int64_t id) {
+    if (!S || id < 0) return EBBKC_E_INVALID_ARG;
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        if (id >= S->next_id) return EBBKC_E_INVALID_ARG;
+        for (auto it = S->pending.begin(); it != S->pending.end(); ++it) {
+            if (it->r.id != id) continue;
+            ebbkc_result r = it->r;
+            S->pending.erase(it);
+            r.status = EBBKC_E_CANCELLED;
+            r.count = 0;
+            r.admit_ms = r.done_ms = S->now_ms();
+            S->done.push_back(r);
+            S->done_cv.notify_all();
+            return EBBKC_OK;
+        }
+        if (S->running.count(id)) {
+            if (std::find(S->cancelled.begin(), S->cancelled.end(), id) == S->cancelled.end())
+                S->cancelled.push_back(id);
+            return EBBKC_OK;
+        }
+    }
+    return EBBKC_E_INVALID_ARG;  // finished already
 }
 
 ebbkc_status ebbkc_server_poll(ebbkc_server* S, ebbkc_result* out, int32_t max, int32_t wait, int32_t* n_out) {

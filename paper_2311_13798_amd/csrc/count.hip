@@ -47,8 +47,10 @@ int opts_of(const ebbkc_options& o) {
 
 // counters: [0..4) per-class work queues, [4,5] total lo/hi, [6] error flags,
 // [12..16) per-class task counts (task generation), [16 + 4 (W-1) ..) search
-// work of width class W (tasks, nodes, word operations)
-constexpr int CNT_WORDS = 32;
+// work of width class W (tasks, nodes, word operations), [32 + 4 (W-1) ..)
+// its waves' end times (sum, latest, count, ~earliest start), [48 + W-1]
+// nodes it handed over through the split queue
+constexpr int CNT_WORDS = 64;
 
 GraphView graph_view(const ebbkc_graph* g) {
     return GraphView{g->rp, g->ci, g->erank, g->rrow, g->orp, g->orow, g->eu, g->ev, g->rank};
@@ -489,6 +491,7 @@ static ebbkc_status read_total(ebbkc_graph* g, uint64_t* out, hipStream_t s) {
     const int err = (int)g->h_counters[6];
     if (err & ERR_WIDTH) return EBBKC_E_WIDTH;
     if (err & ERR_DEPTH) return EBBKC_E_K_RANGE;
+    if (err & ERR_QUEUE) return EBBKC_E_HIP;
     // the exact total is 128 bits wide; the 64-bit result is an error past 2^64
     g->last_total[0] = g->h_counters[4];
     g->last_total[1] = g->h_counters[5];
@@ -496,11 +499,16 @@ static ebbkc_status read_total(ebbkc_graph* g, uint64_t* out, hipStream_t s) {
     if ((err & ERR_OVERFLOW) || g->h_counters[5] != 0) return EBBKC_E_OVERFLOW;
     *out = g->h_counters[4];
     for (int i = 0; i < 4; ++i) g->last_work[i] = 0;
-    for (int W = 1; W <= 4; ++W)
+    for (int W = 1; W <= 4; ++W) {
         for (int i = 0; i < 3; ++i) {
             g->last_work_class[W - 1][i] = g->h_counters[16 + 4 * (W - 1) + i];
             g->last_work[i] += g->last_work_class[W - 1][i];
         }
+        // wave-finish tail: latest end minus the mean end (10 ns ticks)
+        const uint64_t* t = g->h_counters + 32 + 4 * (W - 1);
+        g->last_work_class[W - 1][3] = t[2] ? 10 * (t[1] - t[0] / t[2]) : 0;
+        g->last_work[3] += g->h_counters[48 + W - 1];
+    }
     return EBBKC_OK;
 }
 
@@ -555,7 +563,8 @@ static size_t task_bytes(int64_t n, int64_t T) {
 // contiguous).  list = false: counts (per_task optional); list = true: tuples.
 static ebbkc_status run_tasks(ebbkc_graph* g, int32_t k, const int64_t* tsorted, const uint64_t ccount[4],
                               uint64_t* per_task, const uint64_t* task_off, int32_t* out, void* gframes, bool list,
-                              hipStream_t s, bool noalloc = false) {
+                              hipStream_t s, bool noalloc = false, SplitItem* squeue = nullptr,
+                              unsigned long long* sq = nullptr) {
     // noalloc: no EBBkC-T rank slab and no timing events (the colour-ordered
     // search below the initial branch gives the same count under EBBkC-T)
     const bool truss = !list && !noalloc && g->opt.ordering == EBBKC_ORDER_TRUSS;
@@ -603,6 +612,15 @@ static ebbkc_status run_tasks(ebbkc_graph* g, int32_t k, const int64_t* tsorted,
         a.ev = g->ev;
         a.list_checksums = fused;
         a.gframes = gframes;
+        // runtime splitting: counts only (a queued node's count is not a task's own)
+        if (squeue && !list && !truss && !per_task && g->opt.node_split != -1 && g->opt.blocks_per_cu != -1) {
+            a.squeue = squeue;
+            a.sq = sq;
+            a.split_mode = g->opt.node_split == 1 ? SPLIT_FORCED : SPLIT_ON_DEMAND;
+            a.split_bound = g->opt.node_split == 1 ? 0 : (g->opt.node_split >= 2 ? (uint64_t)g->opt.node_split : 1ull << 16);
+            CHKH(launch_sq_reset(sq, squeue, s));
+        }
+        if (g->opt.count_work && !list && !truss) a.wave_time = (unsigned long long*)(g->d_counters + 32 + 4 * (W - 1));
         CHKH(hipMemsetAsync(a.next, 0, sizeof(uint64_t), s));
         if (ev[W][0]) CHKH(hipEventRecord(ev[W][0], s));
         if (list) {
@@ -627,6 +645,9 @@ static ebbkc_status run_tasks(ebbkc_graph* g, int32_t k, const int64_t* tsorted,
             CHKH(launch_search_truss(W, t, g->cu_count, s));
         } else {
             CHKH(launch_search(W, false, a, g->cu_count, g->opt.blocks_per_cu, s));
+            if (a.squeue)
+                CHKH(hipMemcpyAsync(g->d_counters + 48 + W - 1, sq + SQ_PUSHED, sizeof(uint64_t),
+                                    hipMemcpyDeviceToDevice, s));
         }
         if (ev[W][1]) CHKH(hipEventRecord(ev[W][1], s));
         off += nt;
@@ -745,7 +766,8 @@ static ebbkc_status count_core(ebbkc_graph* g, int32_t k, int64_t r_begin, int64
     CHKH(hipMemcpyAsync(&T, toff + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     CHKH(hipStreamSynchronize(s));
     if (T == 0) return read_total(g, out, s);
-    Carve cv = carve_for(g, src, task_bytes(n, T) + rnd256(fbytes));
+    const size_t qbytes = rnd256((size_t)SQ_CAP * sizeof(SplitItem)) + rnd256(SQ_WORDS * sizeof(uint64_t));
+    Carve cv = carve_for(g, src, task_bytes(n, T) + rnd256(fbytes) + qbytes);
     if (!cv.base) return e_space;
     int64_t* tsorted = nullptr;
     uint64_t ccount[4] = {0, 0, 0, 0};
@@ -754,9 +776,12 @@ static ebbkc_status count_core(ebbkc_graph* g, int32_t k, int64_t r_begin, int64
     if (st) return st == EBBKC_E_OOM ? e_space : st;
     void* gframes = deep ? (void*)cv.take<char>((int64_t)fbytes) : nullptr;
     if (deep && !gframes) return e_space;
+    SplitItem* squeue = cv.take<SplitItem>(SQ_CAP);
+    unsigned long long* sq = cv.take<unsigned long long>(SQ_WORDS);
+    if (!squeue || !sq) return e_space;
 
     // ---- search, one launch per width class
-    st = run_tasks(g, k, tsorted, ccount, nullptr, nullptr, nullptr, gframes, false, s, noalloc);
+    st = run_tasks(g, k, tsorted, ccount, nullptr, nullptr, nullptr, gframes, false, s, noalloc, squeue, sq);
     if (st) return st;
     return read_total(g, out, s);
 }

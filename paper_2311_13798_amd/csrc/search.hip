@@ -18,6 +18,7 @@
 // Nodes with l = 4 or 5 hand their children (l = 2 or 3) to lanes, one child
 // per lane; everything above is wave-uniform with the lanes owning rows.
 #include "arena.h"
+#include "build.h"
 #include "device_util.h"
 
 namespace ebb {
@@ -180,37 +181,89 @@ __device__ __forceinline__ uint64_t lane_edges(const SearchMem<W>& M, const uint
     return e2 / 2;
 }
 
-// Triangles inside Q.  Degrees first; dense Q (missing pairs M <= edges E):
-// T = C(q,3) - M(q-2) + sum_v C(m_v,2) - T_c with m_v the missing pairs at v
-// and T_c the triangles of missing pairs; sparse Q: common out-neighbours
-// along the DAG edges.
+// Triangles inside Q.  Dense Q (missing pairs M <= edges E): T = C(q,3) -
+// M(q-2) + sum_v C(m_v,2) - T_c with m_v the missing pairs at v and T_c the
+// triangles of missing pairs; sparse Q: common out-neighbours along the DAG
+// edges.  dense_hint (the parent set is dense, so Q almost surely is) takes
+// the degrees and T_c in one pass over Q with 32-bit bit iteration, and falls
+// back to the sparse pass if Q turns out sparse after all; otherwise the
+// degrees come first and only the needed pass follows.
 template <int W>
-__device__ __forceinline__ uint64_t lane_triangles(const SearchMem<W>& M, const uint64_t (&Q)[W], uint64_t& ops) {
+__device__ __forceinline__ uint64_t lane_triangles(const SearchMem<W>& M, const uint64_t (&Q)[W], bool dense_hint,
+                                                   uint64_t& ops) {
+    constexpr int H = 2 * W;  // 32-bit halves of a row
     const int q = popcW(Q);
     if (q < 3) return 0;
-    uint32_t e2 = 0, s2 = 0;
-#pragma unroll
-    for (int wz = 0; wz < W; ++wz) {
-        uint64_t bits = Q[wz];
-        while (bits) {
-            const int z = wz * 64 + __builtin_ctzll(bits);
-            bits &= bits - 1;
-            int d = 0;
-#pragma unroll
-            for (int w = 0; w < W; ++w) d += popc64(Q[w] & M.rows[z][w]);
-            e2 += d;
-            const int cm = q - 1 - d;
-            s2 += (uint32_t)(cm * (cm - 1) / 2);
-        }
-    }
     const uint64_t q64 = (uint64_t)q;
-    const uint64_t Mp = (q64 * (q64 - 1) - e2) / 2, E = e2 / 2;
     const uint64_t C3 = q64 * (q64 - 1) * (q64 - 2) / 6;
-    ops += (uint64_t)q * W;
+    uint32_t e2 = 0, s2 = 0, t = 0;
+    if (dense_hint) {
+        uint32_t Qh[H];
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            Qh[2 * w] = (uint32_t)Q[w];
+            Qh[2 * w + 1] = (uint32_t)(Q[w] >> 32);
+        }
+#pragma unroll
+        for (int hz = 0; hz < H; ++hz) {
+            uint32_t bits = Qh[hz];
+            while (bits) {
+                const int b = __builtin_ctz(bits);
+                bits &= bits - 1;
+                const uint32_t* rz = reinterpret_cast<const uint32_t*>(M.rows[32 * hz + b]);
+                uint32_t Cz[H];  // missing pairs z-y inside Q with y > z
+                int d = 0;
+#pragma unroll
+                for (int g = 0; g < H; ++g) {
+                    const uint32_t row = rz[g];
+                    d += __builtin_popcount(Qh[g] & row);
+                    if (g > hz) Cz[g] = Qh[g] & ~row;
+                    else if (g == hz) Cz[g] = Qh[g] & ~row & (b == 31 ? 0u : (~0u << (b + 1)));
+                    else Cz[g] = 0;
+                }
+                e2 += d;
+                const int cm = q - 1 - d;
+                s2 += (uint32_t)(cm * (cm - 1) / 2);
+#pragma unroll
+                for (int gy = hz; gy < H; ++gy) {
+                    while (Cz[gy]) {
+                        const uint32_t* ry = reinterpret_cast<const uint32_t*>(M.rows[32 * gy + __builtin_ctz(Cz[gy])]);
+                        Cz[gy] &= Cz[gy] - 1;
+#pragma unroll
+                        for (int g = gy; g < H; ++g) t += __builtin_popcount(Cz[g] & ~ry[g]);
+                    }
+                }
+            }
+        }
+        const uint64_t Mp = (q64 * (q64 - 1) - e2) / 2, E = e2 / 2;
+        ops += (uint64_t)q * W;
+        if (Mp == 0) return C3;
+        if (Mp <= E) {
+            ops += Mp * W;
+            return C3 - Mp * (q64 - 2) + s2 - t;
+        }
+        t = 0;  // sparse after all: the pass along edges below
+    } else {
+#pragma unroll
+        for (int wz = 0; wz < W; ++wz) {
+            uint64_t bits = Q[wz];
+            while (bits) {
+                const int z = wz * 64 + __builtin_ctzll(bits);
+                bits &= bits - 1;
+                int d = 0;
+#pragma unroll
+                for (int w = 0; w < W; ++w) d += popc64(Q[w] & M.rows[z][w]);
+                e2 += d;
+                const int cm = q - 1 - d;
+                s2 += (uint32_t)(cm * (cm - 1) / 2);
+            }
+        }
+        ops += (uint64_t)q * W;
+    }
+    const uint64_t Mp = (q64 * (q64 - 1) - e2) / 2, E = e2 / 2;
     if (Mp == 0) return C3;
     const bool dense = Mp <= E;
     ops += (dense ? Mp : E) * W;
-    uint32_t t = 0;
 #pragma unroll
     for (int wz = 0; wz < W; ++wz) {
         uint64_t bits = Q[wz];
@@ -405,9 +458,191 @@ const int lane = lane_id();
         return res;
 }
 
+// l-cliques of a t-plex P (every vertex misses at most t-1 others of P),
+// any t, by Algorithm kCtPlex: the vertices adjacent to all others (I, the
+// isolated vertices of the inverse graph) are taken in closed form -- a node
+// (S', C, l') contributes the C(|I|, l') ways to finish S' from I -- and the
+// branching runs on the rest: the child of v_i in C (in order) keeps the
+// vertices of C after v_i that are adjacent to v_i (Eq. kCtPlex: C minus v_1..
+// v_i minus v_i's neighbours in the inverse graph), l' - 1, when it still
+// holds enough vertices with I.  Children with l' - 1 <= 1 are counted at
+// once (l' - 1 = 1: |I| + |C_i|; 0: one clique).  Frames (C, l', last v)
+// live in the child-queue area of LDS: depth <= l <= KCT_MAX_L.
+constexpr int KCT_MAX_L = 96;
+
+template <int W>
+struct KctFrame {
+    uint64_t C[W];
+    int32_t l, cur;
+};
+static_assert(sizeof(KctFrame<4>) * KCT_MAX_L <= 2 * QCAP * sizeof(int32_t), "kCtPlex frames must fit the queue area");
+
+template <int W>
+__device__ u128 tplex_branch_count(SearchMem<W>& M, const uint64_t (&P)[W], int pc, int l, bool& ovf,
+                                   uint64_t& nodes) {
+    const int lane = lane_id();
+    // I: vertices of P adjacent to all others of P
+    uint64_t I[W];
+#pragma unroll
+    for (int q = 0; q < W; ++q) {
+        bool full = false;
+        if ((P[q] >> lane) & 1) {
+            int d = 0;
+#pragma unroll
+            for (int w = 0; w < W; ++w) d += popc64(P[w] & M.rows[lane + 64 * q][w]);
+            full = d == pc - 1;
+        }
+        I[q] = uni64(ballot(full));
+    }
+    const int nI = popcW(I);
+    auto add = [&](u128& acc, u128 x) {
+        acc += x;
+        ovf |= acc < x;
+    };
+    KctFrame<W>* fr = reinterpret_cast<KctFrame<W>*>(&M.pq[0][0]);
+    u128 total = 0;
+    add(total, binom128(nI, l, ovf));  // the root: all l vertices from I
+    int sp = 0;
+    if (lane == 0) {
+#pragma unroll
+        for (int w = 0; w < W; ++w) fr[0].C[w] = P[w] & ~I[w];
+        fr[0].l = l;
+        fr[0].cur = -1;
+    }
+    wave_sync();
+    while (sp >= 0) {
+        uint64_t C[W];
+#pragma unroll
+        for (int w = 0; w < W; ++w) C[w] = uni64(fr[sp].C[w]);
+        const int lf = uniform_i32(fr[sp].l), cur = uniform_i32(fr[sp].cur);
+        int v = -1;  // next vertex of C after cur
+#pragma unroll
+        for (int w = W - 1; w >= 0; --w) {
+            const uint64_t b = C[w] & (cur < 0 ? ~0ull : upper_mask(cur, w));
+            if (b) v = 64 * w + __builtin_ctzll(b);
+        }
+        if (v < 0) {
+            --sp;
+            continue;
+        }
+        if (lane == 0) fr[sp].cur = v;
+        const int lc = lf - 1;
+        ++nodes;
+        if (lc == 0) {
+            add(total, 1);
+            wave_sync();
+            continue;
+        }
+        uint64_t Ci[W];
+#pragma unroll
+        for (int w = 0; w < W; ++w) Ci[w] = C[w] & M.rows[v][w] & upper_mask(v, w);
+        const int ci = popcW(Ci);
+        if (ci + nI < lc) {
+            wave_sync();
+            continue;
+        }
+        if (lc == 1) {  // C(|I|, 1) from I, and each vertex of C_i
+            add(total, (u128)(nI + ci));
+            wave_sync();
+            continue;
+        }
+        add(total, binom128(nI, lc, ovf));  // the child: the rest from I
+        if (lane == 0) {
+#pragma unroll
+            for (int w = 0; w < W; ++w) fr[sp + 1].C[w] = Ci[w];
+            fr[sp + 1].l = lc;
+            fr[sp + 1].cur = -1;
+        }
+        ++sp;
+        wave_sync();
+    }
+    wave_sync();
+    return total;
+}
+
 }  // namespace
 
-template <int W, bool LIST>
+// The build's work areas alias the search's per-vertex scratch, child queue
+// and LDS frames (md .. fr), which the search writes before it reads.
+template <int W>
+constexpr bool build_fits() {
+    return build_scratch_bytes<W>() <= (int)(sizeof(SearchMem<W>) - offsetof(SearchMem<W>, md));
+}
+static_assert(build_fits<1>() && build_fits<2>() && build_fits<3>() && build_fits<4>(),
+              "sub-branch build scratch must fit the search's LDS");
+
+// ---------------------------------------------------------------- split queue
+// Counters are touched once per queue operation, sequentially consistent at
+// device scope, so that a wave that sees no working wave also sees every item
+// pushed before the last one stopped.
+__device__ __forceinline__ unsigned long long sq_load(unsigned long long* p) {
+    return __hip_atomic_load(p, __ATOMIC_SEQ_CST, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned long long sq_add(unsigned long long* p, long long v) {
+    return __hip_atomic_fetch_add(p, (unsigned long long)v, __ATOMIC_SEQ_CST, __HIP_MEMORY_SCOPE_AGENT);
+}
+// longest time a wave waits without work before it gives up with ERR_QUEUE
+// (constant-rate clock of 100 MHz: 60 s), far above any single queued node;
+// also at most SQ_WAIT_SPINS sleeps (each at least 64 * 32 clocks), so the
+// wait ends even if that clock did not advance
+constexpr uint64_t SQ_WAIT_TICKS = 6000000000ull;
+constexpr uint64_t SQ_WAIT_SPINS = 1ull << 26;
+
+// An idle wave claims a queued node: returns its index once its producer has
+// written it, or -1 when no wave is working and the queue is empty (then no
+// item can appear any more: an item is pushed only by a working wave, before
+// that wave stops counting as working) or after SQ_WAIT_TICKS without work
+// (ERR_QUEUE).  A claim takes the head first and counts the wave as working
+// after it; a wave in between may process that node while others have
+// finished, and handles whatever it pushes itself.  Idle polling backs off.
+__device__ int64_t queue_take(const SearchArgs& a) {
+    unsigned long long* sq = a.sq;
+    const uint64_t t0 = wall_clock64();
+    int nap = 1;
+    for (uint64_t spin = 0;; ++spin) {
+        long long got = -1;
+        int done = 0;
+        if (lane_id() == 0) {
+            const unsigned long long h = sq_load(&sq[SQ_HEAD]), r = sq_load(&sq[SQ_RESERVE]);
+            if (h < r && atomicCAS(&sq[SQ_HEAD], h, h + 1) == h) {
+                got = (long long)h;
+                sq_add(&sq[SQ_BUSY], 1);
+                sq_add(&sq[SQ_IDLE], -1);
+            } else if (h >= r && sq_load(&sq[SQ_BUSY]) == 0 && sq_load(&sq[SQ_HEAD]) >= sq_load(&sq[SQ_RESERVE])) {
+                done = 1;
+            } else if (wall_clock64() - t0 > SQ_WAIT_TICKS || spin > SQ_WAIT_SPINS) {
+                atomicOr(a.err, ERR_QUEUE);
+                done = 1;
+            }
+            if (got >= 0) {  // the producer reserved the slot before writing it
+                for (uint64_t wspin = 0;
+                     __hip_atomic_load(&a.squeue[got].ready, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == 0; ++wspin) {
+                    if (wall_clock64() - t0 > SQ_WAIT_TICKS || wspin > SQ_WAIT_SPINS) {
+                        atomicOr(a.err, ERR_QUEUE);
+                        got = -1;
+                        done = 1;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(2);
+                }
+            }
+        }
+        got = (long long)uni64((uint64_t)__shfl(got, 0, 64));
+        done = uniform_i32(__shfl(done, 0, 64));
+        if (got >= 0) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // every lane sees the item
+            return got;
+        }
+        if (done) return -1;
+        for (int i = 0; i < nap; ++i) __builtin_amdgcn_s_sleep(64);
+        nap = nap < 16 ? 2 * nap : 16;
+    }
+}
+
+// BUILD = false: each task's g_i is loaded from the arena.  BUILD = true
+// (batches too large for arenas): the task's slot is its seed edge id in
+// graph task_graph[i], and the wave builds g_i in LDS first (build.h).
+template <int W, bool BUILD>
 __global__ __launch_bounds__(256, (W <= 2 ? 4 : (W <= 3 ? 3 : 2))) void k_search(SearchArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     SearchMem<W>& M = reinterpret_cast<SearchMem<W>*>(smem_raw)[threadIdx.x / 64];
@@ -423,24 +658,59 @@ __global__ __launch_bounds__(256, (W <= 2 ? 4 : (W <= 3 ? 3 : 2))) void k_search
     const bool work = opts & OPT_WORK;
     Acc acc{0, false};
     uint64_t wk_tasks = 0, wk_nodes = 0, wk_ops = 0;
+    const uint64_t t_wave0 = work ? wall_clock64() : 0;
+    // runtime splitting: a wave counts as working from its start until the
+    // static tasks run out, then takes queued nodes until none is left
+    const bool splitting = a.squeue != nullptr;
+    if (splitting && lane == 0) sq_add(&a.sq[SQ_BUSY], 1);
+    bool on_queue = false, took_item = false;
 
     for (;;) {
         unsigned long long it = 0;
-        if (lane == 0) it = atomicAdd(a.next, 1ull);
-        it = uni64(__shfl(it, 0, 64));
-        if ((int64_t)it >= a.ntasks) break;
+        int64_t qitem = -1;
+        if (!on_queue) {
+            if (lane == 0) it = atomicAdd(a.next, 1ull);
+            it = uni64(__shfl(it, 0, 64));
+            if ((int64_t)it >= a.ntasks) {
+                if (!splitting) break;
+                on_queue = true;
+                if (lane == 0) {
+                    sq_add(&a.sq[SQ_IDLE], 1);
+                    sq_add(&a.sq[SQ_BUSY], -1);
+                }
+            }
+        }
+        if (on_queue) {
+            if (took_item && lane == 0) {  // the last queued node is done (its pushes are visible)
+                sq_add(&a.sq[SQ_IDLE], 1);
+                sq_add(&a.sq[SQ_BUSY], -1);
+            }
+            qitem = queue_take(a);
+            if (qitem < 0) break;
+            took_item = true;
+            it = uni64((uint64_t)a.squeue[qitem].it);
+        }
         const int64_t task = a.tasks[it];
         const int64_t slot = task_slot(task);
-        const int x0 = task_x0(task), x1 = task_x1(task);
+        // a queued node is a whole node below the root: every first vertex
+        const int x0 = qitem >= 0 ? 0 : task_x0(task);
+        const int x1 = qitem >= 0 ? 64 * W : task_x1(task);
         const int gi = a.task_graph ? uniform_i32(a.task_graph[it]) : 0;
-        const ArenaView& A = a.views ? a.views[gi] : a.A;
         const int k = a.graph_k ? uniform_i32(a.graph_k[gi]) : a.k;
-        const int c = uniform_i32(A.seed_c[slot]);
+        int c = 0;
+        int64_t ro = 0, vo = 0;
+        if constexpr (BUILD) {
+            c = uniform_i32(a.bviews[gi].subsize[slot]);
+        } else {
+            const ArenaView& A = a.views ? a.views[gi] : a.A;
+            c = uniform_i32(A.seed_c[slot]);
+            ro = A.row_off[slot];
+            vo = A.vtx_off[slot];
+        }
         // t of the closed forms: fixed, or 2 when 2k <= tau and 3 above (Section 6.1)
         const int tau_g = a.graph_tau ? uniform_i32(a.graph_tau[gi]) : a.tau;
         const int tpl = a.tplex > 0 ? a.tplex : (2 * k <= tau_g ? 2 : 3);
-        const bool t2 = et && tpl >= 2, t3 = et && tpl >= 3;
-        const int64_t ro = A.row_off[slot], vo = A.vtx_off[slot];
+        const bool t2 = et && tpl >= 2, t3 = et && tpl >= 3, t4 = et && tpl >= 4;
         wk_tasks += work;
         Acc tacc{0, false};
         if (k == 3) {  // l = 1 at the root: |V(g_i)| triangles through the seed edge
@@ -448,10 +718,46 @@ __global__ __launch_bounds__(256, (W <= 2 ? 4 : (W <= 3 ? 3 : 2))) void k_search
             goto task_done;
         }
 
-        // ---- load the sub-branch into LDS (coalesced)
-        for (int i = lane; i < c * W; i += 64) (&M.rows[0][0])[i] = A.rows[ro + i];
-        for (int i = lane; i < c; i += 64) M.col[i] = A.col[vo + i];
-        wave_sync();
+        if constexpr (BUILD) {
+            // ---- build g_i in LDS, vertices in colour order (build.h)
+            const BuildGraph& B = a.bviews[gi];
+            const BuildScratch<W> S = BuildScratch<W>::carve(&M.md[0]);
+            const int32_t e = (int32_t)slot;
+            uint32_t twoE = 0;
+            if (build_subbranch<W>(B.G, B.G.eu[e], B.G.ev[e], B.G.rank[e], c, B.vcol, M.rows, M.col, S, &twoE) < 0) {
+                if (lane == 0) atomicOr(a.err, ERR_WIDTH);
+                goto task_done;
+            }
+            int npos[W];
+            order_positions<W>(c, M.col, S, npos);
+            uint64_t nr[W][W];
+            int16_t nc[W];
+#pragma unroll
+            for (int q = 0; q < W; ++q) {
+                const int i = lane + 64 * q;
+                nc[q] = 0;
+                if (i < c) {
+                    relabelled_row<W>(M.rows, i, S, nr[q]);
+                    nc[q] = M.col[i];
+                }
+            }
+            wave_sync();
+#pragma unroll
+            for (int q = 0; q < W; ++q) {
+                if (lane + 64 * q < c) {
+#pragma unroll
+                    for (int w = 0; w < W; ++w) M.rows[npos[q]][w] = nr[q][w];
+                    M.col[npos[q]] = nc[q];
+                }
+            }
+            wave_sync();
+        } else {
+            // ---- load the sub-branch into LDS (coalesced)
+            const ArenaView& A = a.views ? a.views[gi] : a.A;
+            for (int i = lane; i < c * W; i += 64) (&M.rows[0][0])[i] = A.rows[ro + i];
+            for (int i = lane; i < c; i += 64) M.col[i] = A.col[vo + i];
+            wave_sync();
+        }
         {
         // colour class lane + 64 q (colour lane + 64 q + 1) occupies the
         // relabelled positions [cs0[q], cs1[q]) = [#(col > colour), #(col >= colour))
@@ -509,6 +815,12 @@ __global__ __launch_bounds__(256, (W <= 2 ? 4 : (W <= 3 ? 3 : 2))) void k_search
                     val = threeplex_count<W>(M, P, pc, l, tacc.ovf);
                     return true;
                 }
+                if (t4 && mind >= pc - tpl && l <= KCT_MAX_L) {
+                    uint64_t kn = 0;
+                    val = tplex_branch_count<W>(M, P, pc, l, tacc.ovf, kn);
+                    if (work) { wk_nodes += kn; wk_ops += kn * W; }
+                    return true;
+                }
             }
             if (l != 3) return false;
             // triangles inside P: dense -> missing-pair identity, sparse -> DAG edges
@@ -552,16 +864,23 @@ __global__ __launch_bounds__(256, (W <= 2 ? 4 : (W <= 3 ? 3 : 2))) void k_search
         // 4-cliques inside R (r >= 4 vertices) from the missing pairs H of R:
         // inclusion-exclusion over the edge sets of H spanning at most four
         // vertices gives K4 = C(r,4) - M C(r-2,2) + P3 (r-3) + 2K2 - T (r-3)
-        // - P4 - S3 + C4 + paw - diamond + K4(H), with P3 the 2-paths, 2K2
-        // the disjoint pairs, T the triangles, P4 the 3-paths, S3 the 3-stars,
-        // C4 the 4-cycles, paw, diamond and K4(H) the remaining 4-vertex
-        // shapes of H.  All but C(r,4) + C(M,2) is a sum over the vertices,
-        // missing pairs and 2-paths of H, taken by the lanes holding them
-        // into S (12 times its value, so that every term is an integer).
-        // Returns false, counting nothing, when H is too dense for this to
-        // beat branching on the pairs of R.
-        auto k4_missing = [&](const uint64_t (&R)[W], int r, bool whole, int64_t& S, uint64_t& uacc) -> bool {
-            // the vertices of R, packed onto consecutive lanes
+        // - P4 - S3 + C4 + paw - diamond + K4(H), with M the missing pairs,
+        // P3 the 2-paths, 2K2 the disjoint pairs, T the triangles, P4 the
+        // 3-paths, S3 the 3-stars, C4 the 4-cycles, paw, diamond and K4(H)
+        // the remaining 4-vertex shapes of H.  With m_v the missing pairs at v
+        // and c(a,b) the common H-neighbours of a and b: P3 = sum C(m_v,2),
+        // S3 = sum C(m_v,3), 2K2 = C(M,2) - P3, and over the pairs of R,
+        // C4 = sum C(c,2) / 2, and over the missing pairs, 3T = sum c,
+        // diamond = sum C(c,2), P4 = sum (m_a-1)(m_b-1) - 3T, paw = sum c
+        // (m_a + m_b - 4) / 2, K4(H) by the H-edges among the common
+        // H-neighbours above b.  The pairs of R are spread evenly over the
+        // lanes (pair index -> (i, j) in closed form), so the work does not
+        // pile up on the vertices with many missing pairs.  Returns false,
+        // counting nothing, when branching on R costs less.
+        auto k4_missing = [&](const uint64_t (&R)[W], int r, bool whole, int64_t& S, uint64_t& uacc,
+                              bool& rdense) -> bool {
+            (void)S;
+            // the vertices of R, packed onto consecutive lanes (ascending)
             {
                 int base = 0;
 #pragma unroll
@@ -572,7 +891,7 @@ __global__ __launch_bounds__(256, (W <= 2 ? 4 : (W <= 3 ? 3 : 2))) void k_search
             }
             wave_sync();
             const int rounds = (r + 63) >> 6;
-            int msum = 0, cm2 = 0, lw = 0;
+            uint32_t msum = 0, cm2 = 0, cm3 = 0;
             for (int t = 0; t < rounds; ++t) {
                 const int j = 64 * t + lane;
                 if (j < r) {
@@ -581,124 +900,92 @@ __global__ __launch_bounds__(256, (W <= 2 ? 4 : (W <= 3 ? 3 : 2))) void k_search
 #pragma unroll
                     for (int w = 0; w < W; ++w) mv += popc64(R[w] & ~M.rows[v][w]);
                     M.md[v] = (int16_t)mv;
-                    msum += mv;
-                    cm2 += mv * (mv - 1) / 2;
-                    lw += mv + mv * (mv - 1) / 2;
+                    msum += (uint32_t)mv;
+                    cm2 += (uint32_t)(mv * (mv - 1) / 2);
+                    cm3 += (uint32_t)(mv * (mv - 1) * (mv - 2) / 6);
                 }
             }
-            const int Msum = (int)wsum_u32((uint32_t)msum);
-            const int64_t P3 = (int64_t)wsum_u32((uint32_t)cm2);
-            // The lanes run in lockstep, so this evaluation takes as long as
-            // its busiest lane (missing pairs + 2-paths at the vertices it
-            // holds, ~15 instructions each) plus ~150 for the reductions.  The
-            // alternative for one R = P & N+(x) of an l = 5 node is one child
-            // y per lane counting the triangles of R & N+(y): ~35 instructions
-            // per vertex of the largest child, ~ r * d, per 64 children (r of
-            // them here, sharing rounds with the other x through the queue);
-            // for a whole l = 4 node it is that for every x (~18 instructions
-            // a step), ~ |E(R)| * d / 64 rounds of 64 children.
-            const int lmax = wmax_i32(lw);
+            const int64_t Msum = (int64_t)wsum_u32(msum);
             const float pairs = 0.5f * (float)r * (float)(r - 1);
             const float E = pairs - 0.5f * (float)Msum, d = E / pairs;
-            const float cost = a.k4_weight * (15.0f * (float)lmax + 150.0f);
+            rdense = 2.0f * E >= pairs;
+            // cost: ~45 instructions per pair of R over 64 lanes, ~150 for the
+            // reductions; the alternative for one R = P & N+(x) of an l = 5
+            // node is one child y per lane counting the triangles of
+            // R & N+(y) (~35 instructions per vertex of the child, ~ r d, per
+            // 64 children); for a whole l = 4 node it is that for every x
+            // (~18 instructions a step, ~ |E(R)| d / 64 rounds)
+            const float cost = a.k4_weight * (45.0f * pairs / 64.0f + 150.0f);
             const float alt = whole ? 18.0f * E * d * (float)r * d / 64.0f
                                     : 35.0f * (float)r * d * (float)r / 64.0f;
             if (!(a.k4_weight > 0.f) || cost > alt) return false;
-            if (work) wk_ops += (uint64_t)(r + Msum + P3) * W;
-            const int64_t Mh = Msum / 2;
-            const uint64_t r64 = (uint64_t)r;
-            uacc += r64 * (r64 - 1) * (r64 - 2) * (r64 - 3) / 24 + (uint64_t)(Mh * (Mh - 1) / 2);
-            if (Msum == 0) return true;
-            wave_sync();  // md[] of every vertex of R
-            const int64_t c2 = (int64_t)(r - 2) * (r - 3) / 2;
-            for (int t = 0; t < rounds; ++t) {
-                const int j = 64 * t + lane;
-                if (j >= r) continue;
-                const int v = M.vl[j];
-                uint64_t hv[W];
-#pragma unroll
-                for (int w = 0; w < W; ++w)
-                    hv[w] = R[w] & ~M.rows[v][w] & (w == (v >> 6) ? ~(1ull << (v & 63)) : ~0ull);
-                const int64_t mv = M.md[v];
-                if (mv == 0) continue;
-                S += -6 * c2 * mv + 12 * (int64_t)(r - 4) * (mv * (mv - 1) / 2) - 2 * mv * (mv - 1) * (mv - 2);
-                // missing pairs v-u: codegree cc in H (triangles, diamonds,
-                // paws), the 3-paths through v-u, K4(H).  Per-v sums in 32 bits:
-                // t2 = sum cc over all u; over u > v: a1 = sum cc, a2 = sum cc^2,
-                // a3 = sum (m_u - 1)
-                int32_t t2 = 0, a1 = 0, a2 = 0, a3 = 0;
-#pragma unroll
-                for (int wu = 0; wu < W; ++wu) {
-                    uint64_t bu = hv[wu];
-                    while (bu) {
-                        const int u = wu * 64 + __builtin_ctzll(bu);
-                        bu &= bu - 1;
-                        uint64_t hu[W];
-#pragma unroll
-                        for (int w = 0; w < W; ++w) hu[w] = R[w] & ~M.rows[u][w];
-                        int cc = -1;  // u lies in both hv and hu
-#pragma unroll
-                        for (int w = 0; w < W; ++w) cc += popc64(hv[w] & hu[w]);
-                        t2 += cc;
-                        if (u > v) {
-                            a1 += cc;
-                            a2 += cc * cc;
-                            a3 += M.md[u] - 1;
-                            if (cc >= 2) {
-                                uint64_t X[W];
-#pragma unroll
-                                for (int w = 0; w < W; ++w) X[w] = hv[w] & hu[w] & upper_mask(u, w);
-#pragma unroll
-                                for (int wx = 0; wx < W; ++wx) {
-                                    while (X[wx]) {
-                                        const int z = wx * 64 + __builtin_ctzll(X[wx]);
-                                        X[wx] &= X[wx] - 1;
-                                        int kk = 0;
-#pragma unroll
-                                        for (int w = 0; w < W; ++w)
-                                            if (w >= wx) kk += popc64(X[w] & ~M.rows[z][w]);
-                                        S += 12 * kk;
-                                    }
-                                }
-                            }
-                        }
-                    }
-                }
-                // per missing pair: 12 (cc - (m_u-1)(m_v-1)) - 4 (r-3) cc - 6 cc (cc-1)
-                S += (int64_t)(18 - 4 * (r - 3)) * a1 - 6 * (int64_t)a2 - 12 * (mv - 1) * (int64_t)a3 +
-                     6 * (int64_t)t2 * (mv - 2);
-                // 2-paths a-v-b (a < b): 4 C4 = sum (codeg(a,b) - 1); with
-                // ha = R & ~row(a), |ha & ~row(b)| = codeg(a,b) + 2 [a-b missing]
-                int32_t wsum = 0;
-#pragma unroll
-                for (int wa = 0; wa < W; ++wa) {
-                    uint64_t ba = hv[wa];
-                    while (ba) {
-                        const int a0 = wa * 64 + __builtin_ctzll(ba);
-                        ba &= ba - 1;
-                        uint64_t ha[W], rest[W];
-                        int corr = 0;
-#pragma unroll
-                        for (int w = 0; w < W; ++w) {
-                            ha[w] = R[w] & ~M.rows[a0][w];
-                            rest[w] = hv[w] & upper_mask(a0, w);
-                            corr += 2 * popc64(rest[w] & ha[w]) + popc64(rest[w]);
-                        }
-                        wsum -= corr;
-#pragma unroll
-                        for (int wb = 0; wb < W; ++wb) {
-                            if (wb < wa) continue;
-                            while (rest[wb]) {
-                                const int b = wb * 64 + __builtin_ctzll(rest[wb]);
-                                rest[wb] &= rest[wb] - 1;
-#pragma unroll
-                                for (int w = 0; w < W; ++w) wsum += popc64(ha[w] & ~M.rows[b][w]);
-                            }
-                        }
-                    }
-                }
-                S += 3 * (int64_t)wsum;
+            const int64_t P3 = (int64_t)wsum_u32(cm2), S3 = (int64_t)wsum_u32(cm3);
+            const int64_t Mh = Msum / 2, rr = r;
+            const int64_t base4 = rr * (rr - 1) * (rr - 2) * (rr - 3) / 24;
+            if (work) wk_ops += (uint64_t)r * W;
+            if (Mh == 0) {
+                uacc += (uint64_t)base4;
+                return true;
             }
+            wave_sync();  // md[] of every vertex of R
+            const int U = r * (r - 1) / 2;
+            const float R2 = 2.0f * (float)r - 1.0f;
+            uint64_t c4 = 0, t3 = 0, dia = 0, p4 = 0, paw = 0, kk = 0;
+            for (int u0 = 0; u0 < U; u0 += 64) {
+                const int u = u0 + lane;
+                if (u >= U) continue;
+                // row i of the upper triangle starts at i (2r - i - 1) / 2
+                int i = (int)((R2 - sqrtf(R2 * R2 - 8.0f * (float)u)) * 0.5f);
+                i = i < 0 ? 0 : (i > r - 2 ? r - 2 : i);
+                while (i < r - 2 && (i + 1) * (2 * r - i - 2) / 2 <= u) ++i;
+                while (i > 0 && i * (2 * r - i - 1) / 2 > u) --i;
+                const int j = u - i * (2 * r - i - 1) / 2 + i + 1;
+                const int va = M.vl[i], vb = M.vl[j];
+                uint64_t ra[W], X[W];
+                int un = 0;
+                bool e = false;
+#pragma unroll
+                for (int w = 0; w < W; ++w) {
+                    ra[w] = M.rows[va][w];
+                    X[w] = R[w] & ~(ra[w] | M.rows[vb][w]);
+                    un += popc64(X[w]);
+                    if (w == (vb >> 6)) e = !((ra[w] >> (vb & 63)) & 1);
+                }
+                // X holds va and vb themselves exactly when they miss each other
+                const int c = un - (e ? 2 : 0);
+                c4 += (uint64_t)(c * (c - 1) / 2);
+                if (e) {
+                    const int ma = M.md[va], mb = M.md[vb];
+                    t3 += (uint64_t)c;
+                    dia += (uint64_t)(c * (c - 1) / 2);
+                    p4 += (uint64_t)((ma - 1) * (mb - 1));
+                    paw += (uint64_t)(c * (ma + mb - 4));
+                    if (c >= 2) {  // K4(H) through (va, vb): H-edges among the common H-neighbours above vb
+#pragma unroll
+                        for (int w = 0; w < W; ++w) X[w] &= upper_mask(vb, w);
+#pragma unroll
+                        for (int wz = 0; wz < W; ++wz) {
+                            uint64_t bz = X[wz];
+                            while (bz) {
+                                const int z = 64 * wz + __builtin_ctzll(bz);
+                                bz &= bz - 1;
+                                int hz = 0;
+#pragma unroll
+                                for (int w = 0; w < W; ++w)
+                                    if (w >= wz) hz += popc64(X[w] & ~M.rows[z][w] & upper_mask(z, w));
+                                kk += (uint64_t)hz;
+                            }
+                        }
+                    }
+                }
+            }
+            if (work) wk_ops += (uint64_t)U * W;
+            const int64_t C4 = (int64_t)wave_sum(c4) / 2, T3 = (int64_t)wave_sum(t3);
+            const int64_t DIA = (int64_t)wave_sum(dia), P4 = (int64_t)wave_sum(p4) - T3;
+            const int64_t PAW = (int64_t)wave_sum(paw) / 2, K4H = (int64_t)wave_sum(kk);
+            const int64_t k4 = base4 - Mh * ((rr - 2) * (rr - 3) / 2) + P3 * (rr - 3) + (Mh * (Mh - 1) / 2 - P3) -
+                               (T3 / 3) * (rr - 3) - P4 - S3 + C4 + PAW - DIA + K4H;
+            uacc += (uint64_t)k4;
             return true;
         };
 
@@ -720,7 +1007,7 @@ __global__ __launch_bounds__(256, (W <= 2 ? 4 : (W <= 3 ? 3 : 2))) void k_search
                     uint64_t Q[W];
 #pragma unroll
                     for (int w = 0; w < W; ++w) Q[w] = P[w] & M.rows[x][w] & M.rows[y][w] & upper_mask(y, w);
-                    if (lc == 3) lsum += lane_triangles(M, Q, lops);
+                    if (lc == 3) lsum += lane_triangles(M, Q, (e >> 25) & 1, lops);
                     else lsum += lane_edges(M, Q);
                 }
             };
@@ -761,7 +1048,8 @@ __global__ __launch_bounds__(256, (W <= 2 ? 4 : (W <= 3 ? 3 : 2))) void k_search
             bool done = false;
             if (l == 4 && xlo == 0 && xhi >= c) {
                 const int pc = popcW(P);
-                done = pc < 4 || k4_missing(P, pc, true, S, usum);
+                bool pd = false;
+                done = pc < 4 || k4_missing(P, pc, true, S, usum, pd);
             }
             int xx = xlo - 1;
             while (!done) {
@@ -779,7 +1067,8 @@ __global__ __launch_bounds__(256, (W <= 2 ? 4 : (W <= 3 ? 3 : 2))) void k_search
                 const int rc = popcW(Rx);
                 if (rc < lc + 1) continue;
                 if (work) { wk_nodes += rc; wk_ops += (uint64_t)rc * W; }
-                if (l == 5 && k4_missing(Rx, rc, false, S, usum)) continue;
+                bool rdense = false;
+                if (l == 5 && k4_missing(Rx, rc, false, S, usum, rdense)) continue;
 #pragma unroll
                 for (int q = 0; q < W; ++q) {
                     const int y = 64 * q + lane;
@@ -789,7 +1078,7 @@ __global__ __launch_bounds__(256, (W <= 2 ? 4 : (W <= 3 ? 3 : 2))) void k_search
                         int qy = 0;  // |Q| of the child (x, y)
 #pragma unroll
                         for (int w = 0; w < W; ++w) qy += popc64(Rx[w] & M.rows[y][w] & upper_mask(y, w));
-                        M.pq[0][qn + popc64(bq & lanemask_lt())] = (qy << 16) | (xx << 8) | y;
+                        M.pq[0][qn + popc64(bq & lanemask_lt())] = (rdense ? 1 << 25 : 0) | (qy << 16) | (xx << 8) | y;
                     }
                     qn += popc64(bq);
                 }
@@ -809,7 +1098,18 @@ __global__ __launch_bounds__(256, (W <= 2 ? 4 : (W <= 3 ? 3 : 2))) void k_search
         // exactly the cliques of that part (so tasks can be listed alone).
         const bool whole = x0 == 0 && x1 >= c;
         bool active = true;
-        if (whole) {
+        int lq = 0;
+        if (qitem >= 0) {
+            // a queued node (finish() already found no closed form for it)
+            lq = uniform_i32(a.squeue[qitem].l);
+            if (lq == 4 || lq == 5) {
+                uint64_t Pn[W];
+#pragma unroll
+                for (int w = 0; w < W; ++w) Pn[w] = uni64(a.squeue[qitem].P[w]);
+                children_by_lanes(Pn, lq, 0, c);
+                active = false;
+            }
+        } else if (whole) {
             u128 rootval = 0;
             active = !finish(P0, l0, rootval);
             if (!active) tacc.add(rootval);
@@ -854,17 +1154,41 @@ __global__ __launch_bounds__(256, (W <= 2 ? 4 : (W <= 3 ? 3 : 2))) void k_search
                 }
             }
         }
-        if (active && (l0 == 4 || l0 == 5)) {
+        if (active && qitem < 0 && (l0 == 4 || l0 == 5)) {
             children_by_lanes(P0, l0, x0, x1);
             active = false;
         }
+        // hand node (Pn, ln), ln >= 4, to an idle wave through the queue
+        // instead of searching it here; true when it was pushed
+        auto try_push = [&](const uint64_t (&Pn)[W], int ln) -> bool {
+            if (!splitting || ln < 4) return false;
+            if (binom(popcW(Pn), ln) < a.split_bound) return false;
+            int ok = 0;
+            if (lane == 0) {
+                unsigned long long* sq = a.sq;
+                const unsigned long long r = sq_load(&sq[SQ_RESERVE]), h = sq_load(&sq[SQ_HEAD]);
+                const bool want = a.split_mode == SPLIT_FORCED || sq_load(&sq[SQ_IDLE]) > r - h;
+                if (want && r + SQ_SLACK < (unsigned long long)SQ_CAP) {
+                    const unsigned long long si = sq_add(&sq[SQ_RESERVE], 1);
+                    SplitItem& I = a.squeue[si];
+                    I.it = (int64_t)it;
+#pragma unroll
+                    for (int w = 0; w < MAX_W; ++w) I.P[w] = w < W ? Pn[w] : 0;
+                    I.l = ln;
+                    __hip_atomic_store(&I.ready, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                    sq_add(&sq[SQ_PUSHED], 1);
+                    ok = 1;
+                }
+            }
+            return uniform_i32(__shfl(ok, 0, 64)) != 0;
+        };
         // depth-first search: the node being branched on lives in registers
         // (P, R, x, l); its ancestors are frames
         int sp = 0;
         uint64_t P[W], R[W];
-        int x = x0 - 1, l = l0;
+        int x = x0 - 1, l = qitem >= 0 ? lq : l0;
 #pragma unroll
-        for (int w = 0; w < W; ++w) { P[w] = P0[w]; R[w] = 0; }
+        for (int w = 0; w < W; ++w) { P[w] = qitem >= 0 ? uni64(a.squeue[qitem].P[w]) : P0[w]; R[w] = 0; }
         while (active) {
             int y = -1;
             while (true) {
@@ -936,6 +1260,7 @@ __global__ __launch_bounds__(256, (W <= 2 ? 4 : (W <= 3 ? 3 : 2))) void k_search
             }
             u128 v = 0;
             if (finish(Pc, lc, v)) { tacc.add(v); continue; }
+            if (try_push(Pc, lc)) continue;
             if (lc == 4 || lc == 5) { children_by_lanes(Pc, lc, 0, c); continue; }
             if (sp >= LDS_FRAMES + (gfr ? GLOBAL_FRAMES : 0)) {
                 if (lane == 0) atomicOr(a.err, ERR_DEPTH);
@@ -965,7 +1290,7 @@ __global__ __launch_bounds__(256, (W <= 2 ? 4 : (W <= 3 ? 3 : 2))) void k_search
             if (a.graph_total) atomicOr(&a.graph_total[2 * gi + 1], 1ull << 63);
             else atomicOr(a.err, ERR_OVERFLOW);
         }
-        if (a.per_task && lane == 0) a.per_task[it] = tacc.lo();
+        if (a.per_task && lane == 0) a.per_task[it] = tacc.lo();  // (no splitting with per-task counts)
         if (a.graph_total) {
             if (lane == 0 && tacc.lo()) {
                 const unsigned long long old = atomicAdd(&a.graph_total[2 * gi], (unsigned long long)tacc.lo());
@@ -981,6 +1306,13 @@ __global__ __launch_bounds__(256, (W <= 2 ? 4 : (W <= 3 ? 3 : 2))) void k_search
         atomicAdd(&a.work[0], (unsigned long long)wk_tasks);
         atomicAdd(&a.work[1], (unsigned long long)wk_nodes);
         atomicAdd(&a.work[2], (unsigned long long)wk_ops);
+        if (a.wave_time) {
+            const unsigned long long t1 = wall_clock64();
+            atomicAdd(&a.wave_time[0], t1);
+            atomicMax(&a.wave_time[1], t1);
+            atomicAdd(&a.wave_time[2], 1ull);
+            atomicMax(&a.wave_time[3], ~(unsigned long long)t_wave0);  // earliest start, complemented
+        }
     }
     if (acc.ovf && lane == 0) atomicOr(a.err, ERR_OVERFLOW);
     if (lane == 0 && acc.v) {
@@ -988,6 +1320,20 @@ __global__ __launch_bounds__(256, (W <= 2 ? 4 : (W <= 3 ? 3 : 2))) void k_search
         const unsigned long long carry = (old + acc.lo() < old) ? 1ull : 0ull;
         if (acc.hi() + carry) atomicAdd(&a.total[1], (unsigned long long)(acc.hi() + carry));
     }
+}
+
+// the split queue's counters and ready flags zeroed before a launch (a kernel,
+// so that captured launch sequences hold no memset node)
+__global__ void k_sq_reset(unsigned long long* sq, SplitItem* items, int64_t cap) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cap; i += (int64_t)gridDim.x * blockDim.x) {
+        if (i < SQ_WORDS) sq[i] = 0;
+        items[i].ready = 0;
+    }
+}
+
+hipError_t launch_sq_reset(unsigned long long* sq, SplitItem* items, hipStream_t s) {
+    hipLaunchKernelGGL(k_sq_reset, dim3(64), dim3(256), 0, s, sq, items, (int64_t)SQ_CAP);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- EBBkC-T
@@ -1207,9 +1553,9 @@ __global__ __launch_bounds__(256, 2) void k_search_truss(TrussArgs a) {
 
 namespace {
 
-template <int W, bool LIST>
+template <int W, bool BUILD>
 int64_t grid_blocks(int64_t ntasks, int cus, int blocks_per_cu) {
-    auto kern = k_search<W, LIST>;
+    auto kern = k_search<W, BUILD>;
     const size_t smem = 4 * sizeof(SearchMem<W>);
     if (hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem) != hipSuccess)
         return -1;
@@ -1230,36 +1576,43 @@ int64_t grid_blocks(int64_t ntasks, int cus, int blocks_per_cu) {
     return grid;
 }
 
-template <int W, bool LIST>
+template <int W, bool BUILD>
 hipError_t launch_w(const SearchArgs& a, int cus, int bpc, hipStream_t s) {
-    const int64_t grid = grid_blocks<W, LIST>(a.ntasks, cus, bpc);
+    const int64_t grid = grid_blocks<W, BUILD>(a.ntasks, cus, bpc);
     if (grid < 0) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_search<W, LIST>), dim3((unsigned)grid), dim3(256), 4 * sizeof(SearchMem<W>), s, a);
+    hipLaunchKernelGGL((k_search<W, BUILD>), dim3((unsigned)grid), dim3(256), 4 * sizeof(SearchMem<W>), s, a);
     return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_search(int W, bool list, const SearchArgs& a, int cus, int bpc, hipStream_t s) {
+hipError_t launch_search(int W, bool build, const SearchArgs& a, int cus, int bpc, hipStream_t s) {
     if (a.ntasks <= 0) return hipSuccess;
-    if (list) return hipErrorInvalidValue;
-    switch (W) {
-        case 1: return launch_w<1, false>(a, cus, bpc, s);
-        case 2: return launch_w<2, false>(a, cus, bpc, s);
-        case 3: return launch_w<3, false>(a, cus, bpc, s);
-        case 4: return launch_w<4, false>(a, cus, bpc, s);
+    if (build && !a.bviews) return hipErrorInvalidValue;
+    switch (W * 2 + (build ? 1 : 0)) {
+        case 2: return launch_w<1, false>(a, cus, bpc, s);
+        case 3: return launch_w<1, true>(a, cus, bpc, s);
+        case 4: return launch_w<2, false>(a, cus, bpc, s);
+        case 5: return launch_w<2, true>(a, cus, bpc, s);
+        case 6: return launch_w<3, false>(a, cus, bpc, s);
+        case 7: return launch_w<3, true>(a, cus, bpc, s);
+        case 8: return launch_w<4, false>(a, cus, bpc, s);
+        case 9: return launch_w<4, true>(a, cus, bpc, s);
     }
     return hipErrorInvalidValue;
 }
 
-int64_t search_grid_waves(int W, bool list, int64_t ntasks, int cus, int bpc) {
-    (void)list;
+int64_t search_grid_waves(int W, bool build, int64_t ntasks, int cus, int bpc) {
     int64_t b = -1;
-    switch (W) {
-        case 1: b = grid_blocks<1, false>(ntasks, cus, bpc); break;
-        case 2: b = grid_blocks<2, false>(ntasks, cus, bpc); break;
-        case 3: b = grid_blocks<3, false>(ntasks, cus, bpc); break;
-        case 4: b = grid_blocks<4, false>(ntasks, cus, bpc); break;
+    switch (W * 2 + (build ? 1 : 0)) {
+        case 2: b = grid_blocks<1, false>(ntasks, cus, bpc); break;
+        case 3: b = grid_blocks<1, true>(ntasks, cus, bpc); break;
+        case 4: b = grid_blocks<2, false>(ntasks, cus, bpc); break;
+        case 5: b = grid_blocks<2, true>(ntasks, cus, bpc); break;
+        case 6: b = grid_blocks<3, false>(ntasks, cus, bpc); break;
+        case 7: b = grid_blocks<3, true>(ntasks, cus, bpc); break;
+        case 8: b = grid_blocks<4, false>(ntasks, cus, bpc); break;
+        case 9: b = grid_blocks<4, true>(ntasks, cus, bpc); break;
     }
     return b < 0 ? -1 : 4 * b;
 }

@@ -10,8 +10,8 @@ import time
 
 import numpy as np
 
-from . import (Graph, ebbkc_server_create, ebbkc_server_destroy, ebbkc_server_poll, ebbkc_server_stats,
-               ebbkc_server_submit)
+from . import (Graph, ebbkc_server_cancel, ebbkc_server_create, ebbkc_server_destroy, ebbkc_server_poll,
+               ebbkc_server_stats, ebbkc_server_submit)
 
 
 def poisson_requests(rate: float, count: int, n_graphs: int, k_lo: int = 3, k_hi: int = 12, seed: int = 1,
@@ -36,6 +36,9 @@ class Server:
 
     def submit(self, graph: int, k: int) -> int:
         return ebbkc_server_submit(self._s, graph, k)
+
+    def cancel(self, rid: int):
+        ebbkc_server_cancel(self._s, rid)
 
     def poll(self, wait: bool = False):
         return ebbkc_server_poll(self._s, 4096, wait)
