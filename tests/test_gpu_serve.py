@@ -153,3 +153,65 @@ def test_a_failing_request_fails_alone(catalogue):
             assert r["status"] == 0 and r["count"] == alone[(g - 2, k)], (g, k)
     K70.close()
     R13.close()
+
+
+def test_budget_forces_admission_to_wait(catalogue):
+    # a budget of one byte: every request exceeds it, so one starts only when no epoch runs (the
+    # admission rule lets a request larger than the budget run alone); epochs never overlap, and
+    # every count is the standalone one
+    from paper_2311_13798_amd.serve import Server
+    ebb, Gs, alone = catalogue
+    S = Server(Gs, 1)
+    rng = np.random.default_rng(12)
+    pairs = [(int(rng.integers(0, len(Gs))), int(rng.integers(3, 9))) for _ in range(40)]
+    ids = [S.submit(g, k) for g, k in pairs]
+    got = {}
+    while len(got) < len(ids):
+        for r in S.poll(wait=True):
+            got[r["id"]] = r
+    st = S.stats()
+    S.close()
+    assert st["epochs"] == len(ids) and st["max_epoch_requests"] == 1
+    spans = sorted((got[i]["admit_ms"], got[i]["done_ms"]) for i in ids)
+    for (a0, d0), (a1, d1) in zip(spans, spans[1:]):
+        assert a1 >= d0  # each epoch started after the previous one was retired
+    for i, (g, k) in zip(ids, pairs):
+        assert got[i]["status"] == 0 and got[i]["count"] == alone[(g, k)]
+
+
+def test_cancel_waiting_and_running_requests():
+    # with a one-byte budget requests wait behind a long one (R-MAT s13 at k = 12, ~2 s): a waiting
+    # request is withdrawn at once, the running one reports EBBKC_E_CANCELLED at its end, the others
+    # keep their counts, and a finished request cannot be cancelled
+    import time
+
+    import torch
+    import paper_2311_13798_amd as ebb
+    from paper_2311_13798_amd.serve import Server
+    torch.cuda.set_device(0)
+    heavy = ebb.Graph.from_csr(configs.rmat_scale(13))
+    gl = graphgen.er_planted(300, 0.05, 1, 25, 25, 2)
+    light = ebb.Graph.from_csr(gl)
+    want = {k: oracle.count(gl, k) for k in range(3, 8)}
+    S = Server([heavy, light], 1)
+    hid = S.submit(0, 12)
+    time.sleep(0.2)  # the long request is running
+    lids = [S.submit(1, k) for k in range(3, 8)]
+    S.cancel(lids[2])  # still waiting
+    S.cancel(hid)
+    got = {}
+    while len(got) < len(lids) + 1:
+        for r in S.poll(wait=True):
+            got[r["id"]] = r
+    assert got[lids[2]]["status"] == ebb.E_CANCELLED and got[lids[2]]["count"] == 0
+    assert got[lids[2]]["done_ms"] <= got[hid]["done_ms"]  # withdrawn while the long one ran
+    assert got[hid]["status"] == ebb.E_CANCELLED
+    for i, k in zip(lids, range(3, 8)):
+        if i != lids[2]:
+            assert got[i]["status"] == 0 and got[i]["count"] == want[k]
+    with pytest.raises(ebb.EbbkcError) as ei:
+        S.cancel(lids[0])
+    assert ei.value.status == ebb.E_INVALID_ARG
+    S.close()
+    heavy.close()
+    light.close()
