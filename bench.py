@@ -231,6 +231,150 @@ def batched_leg(ebb, torch, configs, ngraphs=512, scale=0.1):
     return out, Gs
 
 
+def batch_full(ebb, torch, configs, count=4096, threads=16):
+    """The batched workload at its stated size (4,096 graphs, n U{50..5000}): one launch per graph (the
+    plain kernel: ebbkc_count on each prepared graph, whose first count builds its sub-branch arena;
+    graphs are prepared, counted and released one at a time) against the fused batch of all graphs
+    resident at once (tasks build their sub-branches in LDS, since the arenas would need about
+    700 GB), both timed around the counting only, with every count checked against the oracle's
+    stored value when tests/golden/batch4096.json is present."""
+    import concurrent.futures as cf
+    params = configs.batch_params(4096)[:count]
+    gold_path = os.path.join(ROOT, "tests", "golden", "batch4096.json")
+    gold = {}
+    if os.path.exists(gold_path):
+        gold = {r["index"]: int(r["count"]) for r in json.load(open(gold_path))["graphs"]}
+
+    def graphs(part):
+        with cf.ThreadPoolExecutor(max_workers=threads) as ex:
+            return list(ex.map(configs.batch_graph, part))
+
+    t_plain, plain, t_prep = 0.0, [], 0.0
+    for i0 in range(0, len(params), 256):
+        part = params[i0:i0 + 256]
+        for p, g in zip(part, graphs(part)):
+            t = time.perf_counter()
+            G = ebb.Graph.from_csr(g)
+            torch.cuda.synchronize()
+            t_prep += time.perf_counter() - t
+            t = time.perf_counter()
+            plain.append(G.count(int(p["k"])))
+            t_plain += time.perf_counter() - t
+            G.close()
+        log(f"batch-full plain {len(plain)} graphs: {t_plain:.1f} s counting, {t_prep:.1f} s preparing")
+    Gs, ks = [], []
+    for i0 in range(0, len(params), 256):
+        part = params[i0:i0 + 256]
+        for p, g in zip(part, graphs(part)):
+            Gs.append(ebb.Graph.from_csr(g))
+            ks.append(int(p["k"]))
+    torch.cuda.synchronize()
+    o = ebb.ebbkc_default_options()
+    o.batch_build = ebb.BATCH_BUILD
+    t = time.perf_counter()
+    B = ebb.Batch(Gs, ks, options=o)
+    t_create = time.perf_counter() - t
+    B.run(use_graph=True)  # capture
+    t = time.perf_counter()
+    got = B.run(use_graph=True)
+    t_batch = time.perf_counter() - t
+    tasks = B.info()[0]
+    B.close()
+    m_total = sum(int(G.info.m) for G in Gs)
+    for G in Gs:
+        G.close()
+    tot = sum(plain)
+    want = [gold.get(p["index"]) for p in params]
+    out = {"graphs": len(params), "edges": m_total, "tasks": tasks,
+           "workload": "the batched workload at its stated size: graph i from seed splitmix64(1 ^ i), n U{50..5000}, "
+                       "p U[0.005,0.2], 20% with one planted clique of U{20..40}, k U{3..10}",
+           "kcliques": tot, "plain_s": round(t_plain, 4), "batched_s": round(t_batch, 4),
+           "batch_create_s": round(t_create, 4), "prepare_s": round(t_prep, 4),
+           "plain_kcliques_per_s": tot / t_plain, "batched_kcliques_per_s": tot / t_batch,
+           "vs_plain": round(t_plain / t_batch, 3), "identical": got == plain,
+           "equal_to_oracle": (got == want) if all(w is not None for w in want) else None}
+    log(f"batch-full: plain {t_plain:.1f}s fused {t_batch:.1f}s identical={got == plain} oracle={out['equal_to_oracle']}")
+    return out
+
+
+def served_full(ebb, torch, configs, rates=(50, 100, 200, 500, 1000, 2000), count=2000, cap_s=1.0,
+                budget=1 << 36):
+    """The served workload at its stated shape: a resident catalogue of R-MAT s12..s18, Chung-Lu
+    n = 1e4, 3e4, 1e5, 3e5, 1e6 (200 n / 1e6 planted cliques, at least 2), ER(2000, 0.01) and the first
+    64 graphs of the batched workload at full size; requests (graph, k) uniform over the pairs with
+    3 <= k <= 12 whose standalone count takes at most cap_s (k grows per graph until a count exceeds
+    it); Poisson arrivals at each rate, `count` requests each.  Every result is compared with its
+    standalone count, and the standalone counts with every stored oracle value there is."""
+    import concurrent.futures as cf
+    from paper_2311_13798_amd.serve import Server, poisson_requests, summarize
+    named = [(f"rmat{s}", lambda s=s: configs.rmat_scale(s)) for s in range(12, 19)]
+    named += [(f"cl{n:g}", lambda n=n: configs.cl_planted(n)) for n in (10000, 30000, 100000, 300000, 1000000)]
+    named += [("er2000", configs.er_small)]
+    params = configs.batch_params(4096)[:64]
+    with cf.ThreadPoolExecutor(max_workers=16) as ex:
+        c4 = list(ex.map(configs.batch_graph, params))
+    graphs = [(n, mk()) for n, mk in named] + [(f"batch{p['index']}", g) for p, g in zip(params, c4)]
+    gold = {}  # (graph name, k) -> oracle count
+    gdir = os.path.join(ROOT, "tests", "golden")
+
+    def load(name):
+        path = os.path.join(gdir, name)
+        return json.load(open(path)) if os.path.exists(path) else None
+    r18, cl, er, sv, b4 = (load(f) for f in ("rmat18.json", "cl1m.json", "er_small.json", "served.json", "batch4096.json"))
+    for rec, name in ((r18, "rmat18"), (cl, "cl1e+06"), (er, "er2000")):
+        if rec:
+            for k, v in rec["counts"].items():
+                gold[(name, int(k))] = int(v)
+    k8 = load("rmat18_k8.json")
+    if k8:
+        gold[("rmat18", 8)] = int(k8["count"])
+    if sv:
+        for k, v in sv["graphs"]["rmat13"]["counts"].items():
+            gold[("rmat13", int(k))] = int(v)
+    if b4:
+        for r in b4["graphs"][:64]:
+            gold[(f"batch{r['index']}", int(r["k"]))] = int(r["count"])
+    Gs = [ebb.Graph.from_csr(g) for _, g in graphs]
+    names = [n for n, _ in graphs]
+    alone, secs, pairs = {}, {}, []
+    for i, G in enumerate(Gs):
+        for k in range(3, 13):
+            t = time.perf_counter()
+            v = G.count(k)
+            dt = time.perf_counter() - t
+            if dt > cap_s:
+                secs[f"{names[i]}@{k}"] = round(dt, 3)
+                break
+            alone[(i, k)] = v
+            pairs.append((i, k))
+        log(f"served-full catalogue {names[i]}: k <= {max(k for j, k in pairs if j == i)}")
+    checked = [(names[i], k) for i, k in pairs if (names[i], k) in gold]
+    oracle_ok = all(alone[(names.index(n), k)] == gold[(n, k)] for n, k in checked)
+    out = {"catalogue": names, "k": "3..12, per graph up to the last k whose standalone count takes at most "
+                                    f"{cap_s} s", "pairs": len(pairs), "budget_bytes": budget,
+           "excluded_first_pair_seconds": secs, "pairs_checked_against_oracle": len(checked),
+           "standalone_equal_to_oracle": oracle_ok, "rates": {}}
+    rng_pairs = pairs
+    for rate in rates:
+        S = Server(Gs, budget)
+        reqs = poisson_requests(rate=float(rate), count=count, n_graphs=len(rng_pairs), k_lo=3, k_hi=3, seed=rate)
+        reqs = [(off, rng_pairs[j][0], rng_pairs[j][1]) for off, j, _ in reqs]
+        res = S.run_stream(reqs)
+        st = S.stats()
+        S.close()
+        sm = summarize(res)
+        same = all(r["status"] == 0 and r["count"] == alone[(g, k)] for (o, g, k), r in zip(reqs, res))
+        out["rates"][str(rate)] = {"requests": count, "p50_ms": round(sm["p50_ms"], 4), "p99_ms": round(sm["p99_ms"], 4),
+                                   "mean_ms": round(sm["mean_ms"], 4), "makespan_s": round(sm["makespan_s"], 3),
+                                   "kcliques_per_s": sm["kcliques_per_s"], "epochs": st["epochs"],
+                                   "max_requests_per_epoch": st["max_epoch_requests"], "identical_to_alone": same}
+        log(f"served-full {rate} req/s: p50 {sm['p50_ms']:.2f} ms p99 {sm['p99_ms']:.1f} ms "
+            f"{sm['kcliques_per_s']:.3e} k-cliques/s identical={same}")
+    for G in Gs:
+        G.close()
+    return out
+
+
 def served_leg(ebb, configs, Gs, rates, budget_s, est_per_rate_s=25.0):
     """Poisson request streams over a resident catalogue (R-MAT s12, s13, Chung-Lu 1e4..3e5,
     ER(2000, 0.01) and 64 of the batched graphs), k U{3..12}; every result compared with the same
@@ -345,6 +489,10 @@ def main():
     ap.add_argument("--traffic-record", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "OUT_JSON"))
     ap.add_argument("--traffic-k", type=int, default=9)
     ap.add_argument("--traffic-command", default="")
+    ap.add_argument("--batch-full", action="store_true",
+                    help="only the batched workload at its stated size (4,096 graphs), plain vs fused")
+    ap.add_argument("--served-full", action="store_true",
+                    help="only the served workload at its stated shape (full catalogue, six rates)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU sharding of this "
@@ -356,6 +504,22 @@ def main():
         return
     if args.traffic_run:
         traffic_run(args.traffic_k)
+        return
+    if args.batch_full:
+        import torch
+
+        import paper_2311_13798_amd as ebb
+        from graphgen import configs
+        torch.cuda.set_device(0)
+        print(json.dumps({"batched_full": batch_full(ebb, torch, configs)}), flush=True)
+        return
+    if args.served_full:
+        import torch
+
+        import paper_2311_13798_amd as ebb
+        from graphgen import configs
+        torch.cuda.set_device(0)
+        print(json.dumps({"served_full": served_full(ebb, torch, configs)}), flush=True)
         return
     ks = [int(x) for x in args.ks.split(",") if x]
 
@@ -429,7 +593,9 @@ def main():
                 "traffic": traffic_for(kernel, kd), "word_ops_per_launch": word_ops,
                 "nodes_per_launch": int(np.mean([r["work"][kd][wd - 1][1] for r in runs])),
                 "tasks_per_launch": int(np.mean([r["work"][kd][wd - 1][0] for r in runs])),
-                "launch_ms": round(dom_ms, 3)}
+                "launch_ms": round(dom_ms, 3),
+                # the launch's last wave ends this long after the mean wave end
+                "wave_tail_ms": round(float(np.mean([r["work"][kd][wd - 1][3] for r in runs])) / 1e6, 3)}
 
     line = {
         "metric": METRIC, "value": total / (ms_per_step / 1e3), "unit": "k-cliques/s", "n_gpus": 1,
