@@ -412,11 +412,13 @@ def served_leg(ebb, configs, Gs, rates, budget_s, est_per_rate_s=25.0):
 
 def ablation(ebb, torch, configs, graphgen):
     """Variants of the path on the same engine (Section 6.2 (3)-(5), (7)): orderings H (default), C, T
-    and the edge- and node-parallel VBBkC roots, Rule (2) off, early termination off, t fixed to 1, 3.  Times
+    and the edge- and node-parallel VBBkC roots, Rule (2) off, early termination off, t fixed to 1..5 (the
+    t sweep of Section 6.2 (6); t >= 4 through kCtPlex branching).  Times
     are wall-clock per count on the prepared graph (arena built beforehand); a variant stops at the
     first k over 10 s, and a refused count (sub-branch wider than 256) is reported as such."""
     variants = [("H", {}), ("H-no-rule2", {"rule2": 0}), ("H-no-ET", {"early_termination": 0}),
-                ("H-t1", {"t_plex": 1}), ("H-t3", {"t_plex": 3}), ("C", {"ordering": 1}),
+                ("H-t1", {"t_plex": 1}), ("H-t2", {"t_plex": 2}), ("H-t3", {"t_plex": 3}), ("H-t4", {"t_plex": 4}),
+                ("H-t5", {"t_plex": 5}), ("C", {"ordering": 1}),
                 ("VBBkC-EP", {"ordering": 2, "rule2": 0}), ("VBBkC-NP", {"ordering": 4, "rule2": 0}),
                 ("T", {"ordering": 3})]
     graphs = [("R-MAT s12", lambda: graphgen.rmat(12, 16, seed=1), (6, 7, 8, 9, 10)),

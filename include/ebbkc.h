@@ -135,7 +135,14 @@ typedef struct {
                                   queue at every depth); -1: off.  Not used by listings, per-seed
                                   counts, EBBkC-T or non-persistent launches (blocks_per_cu = -1).
                                   Counts are the same. */
-    int32_t reserved[3];
+    int32_t adj_max_n;         /* sub-branch builds (Eq. edge-oriented-branching: the edges among
+                                  V(g_i) ranked after e_i): graphs with at most this many vertices
+                                  get an adjacency bitmap of G at prepare (n^2 / 8 bytes plus a
+                                  quarter of that), and every pair of V(g_i) is tested against it
+                                  (about |V(g_i)|^2 / 2 tests instead of a scan of every member's
+                                  row); larger graphs scan.  0 (default): 8192; -1: never; at most
+                                  32768, else EBBKC_E_INVALID_ARG.  Counts are the same. */
+    int32_t reserved[2];
 } ebbkc_options;
 
 enum { EBBKC_BATCH_AUTO = 0, EBBKC_BATCH_ARENA = 1, EBBKC_BATCH_BUILD = 2 };
@@ -319,10 +326,16 @@ ebbkc_status ebbkc_batch_create(ebbkc_graph *const *graphs, const int32_t *ks, i
 ebbkc_status ebbkc_batch_run(ebbkc_batch *b, int32_t use_graph, uint64_t *out_counts, void *stream);
 
 /* Autotuner: times the batch under split thresholds {2^16, 2^22, 2^28, never}
- * x workgroups per CU {auto, 1, 2, not persistent}, checks every setting gives the same
- * counts, keeps the fastest (also in the process cache and, if the
- * environment names one, the EBBKC_TUNE_CACHE file). */
-ebbkc_status ebbkc_batch_tune(ebbkc_batch *b, void *stream, int32_t *out_split, int32_t *out_blocks_per_cu);
+ * (only the current one when the batch's tasks build their sub-branches, one
+ * task per seed) x workgroups per CU {auto, 1, 2, not persistent}, then, with
+ * the fastest of those, the runtime node split bounds {off, 2^10, 2^16, 2^22}
+ * (ebbkc_options.node_split: how small a node may still be handed to an idle
+ * wave, i.e. how deep a branch is spread over waves); checks every setting
+ * gives the same counts and keeps the fastest (also in the process cache and,
+ * if the environment names one, the EBBKC_TUNE_CACHE file).  Any out pointer
+ * may be NULL. */
+ebbkc_status ebbkc_batch_tune(ebbkc_batch *b, void *stream, int32_t *out_split, int32_t *out_blocks_per_cu,
+                              int32_t *out_node_split);
 
 /* Number of tasks and the host wall time (ms) of the last run. */
 ebbkc_status ebbkc_batch_info(const ebbkc_batch *b, int64_t *out_tasks, double *out_last_ms);

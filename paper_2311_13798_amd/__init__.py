@@ -38,7 +38,8 @@ class ebbkc_options(ctypes.Structure):
                 ("rule2", ctypes.c_int32), ("waves_per_block", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
                 ("split_threshold", ctypes.c_int32), ("count_work", ctypes.c_int32),
                 ("dense_k4", ctypes.c_int32), ("ordering", ctypes.c_int32), ("batch_build", ctypes.c_int32),
-                ("node_split", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("node_split", ctypes.c_int32), ("adj_max_n", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
 class ebbkc_result(ctypes.Structure):
@@ -91,7 +92,8 @@ def load_library(path: str = LIB_PATH):
     lib.ebbkc_destroy.restype = None
     lib.ebbkc_batch_create.argtypes = [vp, vp, i32, ctypes.POINTER(ebbkc_options), vp, ctypes.POINTER(vp)]
     lib.ebbkc_batch_run.argtypes = [vp, i32, vp, vp]
-    lib.ebbkc_batch_tune.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
+    lib.ebbkc_batch_tune.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                     ctypes.POINTER(ctypes.c_int32)]
     lib.ebbkc_batch_info.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)]
     lib.ebbkc_batch_destroy.argtypes = [vp]
     lib.ebbkc_batch_destroy.restype = None
@@ -272,9 +274,10 @@ def ebbkc_batch_run(b, use_graph: bool = True, stream=None):
 
 
 def ebbkc_batch_tune(b, stream=None):
-    sp, bp = ctypes.c_int32(), ctypes.c_int32()
-    _check(load_library().ebbkc_batch_tune(b, _stream(stream), ctypes.byref(sp), ctypes.byref(bp)), "ebbkc_batch_tune")
-    return int(sp.value), int(bp.value)
+    sp, bp, ns = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(load_library().ebbkc_batch_tune(b, _stream(stream), ctypes.byref(sp), ctypes.byref(bp), ctypes.byref(ns)),
+           "ebbkc_batch_tune")
+    return int(sp.value), int(bp.value), int(ns.value)
 
 
 def ebbkc_batch_info(b):

@@ -43,7 +43,7 @@ void ebbkc_destroy(ebbkc_graph* g) {
     (void)hipSetDevice(g->device);
     void* ptrs[] = {g->rp, g->ci, g->erank, g->eu, g->ev, g->sup0, g->rank, g->level, g->rrow, g->orp, g->orow,
                     g->byrank, g->subsize, g->scratch, g->d_counters, g->seed_eid, g->seed_c, g->row_off,
-                    g->vtx_off, g->arows, g->agid, g->acol, g->nedges, g->vpos, g->vcol, g->rho_slab,
+                    g->vtx_off, g->arows, g->agid, g->acol, g->nedges, g->vpos, g->vcol, g->rho_slab, g->adj, g->acum,
                     g->varena.seed_v, g->varena.seed_c, g->varena.seed_rthr, g->varena.row_off,
                     g->varena.vtx_off, g->varena.rows, g->varena.gid, g->varena.col, g->varena.nedges};
     for (void* p : ptrs)
@@ -67,7 +67,7 @@ ebbkc_status ebbkc_prepare(const int32_t* row_ptr, const int32_t* col_idx, int32
     if (opt) g->opt = *opt; else ebbkc_default_options(&g->opt);
     if (g->opt.ordering < EBBKC_ORDER_HYBRID || g->opt.ordering > EBBKC_ORDER_DEGEN_VERTEX_NP ||
         g->opt.batch_build < EBBKC_BATCH_AUTO || g->opt.batch_build > EBBKC_BATCH_BUILD || g->opt.node_split < -1 ||
-        g->opt.t_plex < 0 || g->opt.t_plex > 16) {
+        g->opt.t_plex < 0 || g->opt.t_plex > 16 || g->opt.adj_max_n < -1 || g->opt.adj_max_n > ebb::ADJ_MAX_N) {
         delete g;
         return EBBKC_E_INVALID_ARG;
     }

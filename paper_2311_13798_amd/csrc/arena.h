@@ -10,11 +10,13 @@ namespace ebb {
 enum : int { ERR_WIDTH = 1, ERR_OVERFLOW = 2, ERR_DEPTH = 4, ERR_CAP = 8, ERR_QUEUE = 16 };
 enum : int { OPT_ET = 1, OPT_RULE1 = 4, OPT_RULE2 = 8, OPT_WORK = 16 };
 
-constexpr int MAX_W = 4;              // widest bitmap class: 256 vertices
-constexpr int LIST_FUSED_K = 8;       // listings up to this k sort and hash tuples as they are written
-constexpr int LDS_FRAMES = 12;        // search frames kept in LDS (nodes with l >= 6)
-constexpr int GLOBAL_FRAMES = 124;    // further frames in device memory, per wave
-constexpr int LIST_LDS_FRAMES = 16;   // listing frames kept in LDS
+constexpr int MAX_W = 4;                 // widest bitmap class: 256 vertices
+constexpr int ADJ_DEFAULT_MAX_N = 8192;  // graphs up to this many vertices get an adjacency bitmap
+constexpr int ADJ_MAX_N = 32768;         // largest bound the option accepts (128 MB bitmap)
+constexpr int LIST_FUSED_K = 8;          // listings up to this k sort and hash tuples as they are written
+constexpr int LDS_FRAMES = 12;           // search frames kept in LDS (nodes with l >= 6)
+constexpr int GLOBAL_FRAMES = 124;       // further frames in device memory, per wave
+constexpr int LIST_LDS_FRAMES = 16;      // listing frames kept in LDS
 // a search at k needs device-memory frames past these k (count kernel,
 // listing kernel); a listing runs both kernels
 constexpr int SEARCH_DEEP_K = 2 + 2 * LDS_FRAMES + 4;
@@ -32,6 +34,12 @@ struct GraphView {
     const int32_t* eu;
     const int32_t* ev;
     const int32_t* rank;
+    // adjacency bitmap of G (graphs of at most a few thousand vertices; null
+    // otherwise): row x holds adjw words, bit w set for every neighbour w;
+    // acum[x adjw + q] = entries of x's id-sorted row below vertex 64 q
+    const uint64_t* adj;
+    const uint16_t* acum;
+    int32_t adjw;
 };
 
 // Seeds are the edges with |V(g_i)| >= 1 in rank order; slot s of the arena
@@ -116,10 +124,12 @@ struct SplitItem {
     int32_t l;
     int32_t ready;  // 1 once the item is written (release store)
 };
-// queue counters: [SQ_HEAD] items claimed, [SQ_RESERVE] items reserved,
-// [SQ_BUSY] waves working (a wave counts itself when it starts), [SQ_IDLE]
-// waves waiting for items, [SQ_PUSHED] items pushed over the launch
-enum : int { SQ_HEAD = 0, SQ_RESERVE = 1, SQ_BUSY = 2, SQ_IDLE = 3, SQ_PUSHED = 4, SQ_WORDS = 8 };
+// queue counters, each on a 128-byte line of its own (waiting waves poll
+// them while working waves update them): [SQ_HEAD] items claimed,
+// [SQ_RESERVE] items reserved, [SQ_BUSY] waves working (a wave counts itself
+// when it starts), [SQ_IDLE] waves waiting for items, [SQ_PUSHED] items
+// pushed over the launch
+enum : int { SQ_HEAD = 0, SQ_RESERVE = 16, SQ_BUSY = 32, SQ_IDLE = 48, SQ_PUSHED = 64, SQ_WORDS = 80 };
 constexpr int64_t SQ_CAP = 1 << 16;        // items per launch
 constexpr int64_t SQ_SLACK = 1 << 13;       // more than the waves of one launch
 constexpr int SPLIT_OFF = 0, SPLIT_ON_DEMAND = 1, SPLIT_FORCED = 2;

@@ -9,9 +9,11 @@
 // graph.  Each task adds its count to its own graph's exact 128-bit total.
 //
 // Autotuning: ebbkc_batch_tune times the batch under a few (split threshold,
-// workgroups per CU) settings and keeps the fastest; the choice is cached per
-// batch signature for the process (and in the file named by EBBKC_TUNE_CACHE
-// when that variable is set).
+// workgroups per CU) settings, then, with the best of those, a few bounds for
+// handing search nodes to idle waves at run time (how deep a branch is split
+// over waves), and keeps the fastest; the choice is cached per batch
+// signature for the process (and in the file named by EBBKC_TUNE_CACHE when
+// that variable is set).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -98,9 +100,12 @@ __global__ void k_btask_counts(const int32_t* __restrict__ seed_c, int64_t n, in
     }
 }
 
+// Sort key of a task: width class, then (gbits > 0) its graph, then the
+// vertices it can still use, largest first.
 __global__ void k_btask_fill(const int32_t* __restrict__ seed_c, int64_t n, int l0, double log_thr,
-                             const int64_t* __restrict__ toff, int64_t base, int32_t graph, int64_t* __restrict__ tasks,
-                             int32_t* __restrict__ tgraph, uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+                             const int64_t* __restrict__ toff, int64_t base, int32_t graph, int gbits,
+                             int64_t* __restrict__ tasks, int32_t* __restrict__ tgraph, uint64_t* __restrict__ keys,
+                             uint32_t* __restrict__ vals) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         const int c = seed_c[i];
         if (c < l0) continue;
@@ -110,7 +115,8 @@ __global__ void k_btask_fill(const int32_t* __restrict__ seed_c, int64_t n, int 
             tasks[o] = task_pack(i, x0, x1);
             tgraph[o] = graph;
             const int usable = x0 == 0 && x1 >= c ? c : c - 1 - x0;
-            keys[o] = ((uint64_t)(W - 1) << 8) | (uint64_t)(255 - (usable > 255 ? 255 : usable));
+            keys[o] = ((uint64_t)(W - 1) << (8 + gbits)) | ((uint64_t)(gbits ? graph : 0) << 8) |
+                      (uint64_t)(255 - (usable > 255 ? 255 : usable));
             vals[o] = (uint32_t)o;
             ++o;
         });
@@ -126,9 +132,10 @@ __global__ void k_bgather(const int64_t* __restrict__ tasks, const int32_t* __re
     }
 }
 
-__global__ void k_bclass_hist(const uint64_t* __restrict__ keys, int64_t n, unsigned long long* __restrict__ cls) {
+__global__ void k_bclass_hist(const uint64_t* __restrict__ keys, int64_t n, int gbits,
+                              unsigned long long* __restrict__ cls) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        atomicAdd(&cls[(keys[i] >> 8) & 3], 1ull);
+        atomicAdd(&cls[(keys[i] >> (8 + gbits)) & 3], 1ull);
 }
 
 // zero the counters and per-graph totals (a kernel, so the captured graph
@@ -160,7 +167,8 @@ __global__ void k_arena_bytes(const int32_t* __restrict__ subsize, int64_t m, un
 }
 
 GraphView graph_arrays(const ebbkc_graph* g) {
-    return GraphView{g->rp, g->ci, g->erank, g->rrow, g->orp, g->orow, g->eu, g->ev, g->rank};
+    return GraphView{g->rp, g->ci, g->erank, g->rrow, g->orp, g->orow, g->eu, g->ev, g->rank,
+                     g->adj, g->acum, g->adjw};
 }
 
 int opts_of(const ebbkc_options& o) {
@@ -196,7 +204,9 @@ ebbkc_status build_tasks(ebbkc_batch* b, hipStream_t s) {
     free_tasks(b);
     const int n = (int)b->graphs.size();
     const double thr = b->opt.split_threshold > 0 ? (double)b->opt.split_threshold : (double)(1 << 22);
-    const double log_thr = b->opt.split_threshold < 0 ? 1e300 : std::log(thr);
+    // a task that builds its g_i would rebuild it for every root range: one
+    // task per seed there (the runtime split queue balances heavy ones)
+    const double log_thr = b->opt.split_threshold < 0 || b->build ? 1e300 : std::log(thr);
     // per graph: task counts and offsets (scratch sized for the largest graph)
     std::vector<int64_t> gbase((size_t)n + 1, 0);
     std::vector<int64_t*> toffs((size_t)n, nullptr);
@@ -249,19 +259,24 @@ ebbkc_status build_tasks(ebbkc_batch* b, hipStream_t s) {
     CHKB(dev_alloc(b, (void**)&vals2, sizeof(uint32_t) * total, s));
     CHKB(dev_alloc(b, (void**)&hist, sizeof(int64_t) * hn, s));
     CHKB(dev_alloc(b, (void**)&htmp, sizeof(int64_t) * (scan_tmp_elems(hn) + 64), s));
+    // tasks that build their g_i run graph by graph within a width class, so
+    // that the waves of a launch share one graph's arrays in cache
+    int gbits = 0;
+    if (b->build)
+        while (((int64_t)1 << gbits) < (int64_t)n) ++gbits;
     for (int i = 0; i < n; ++i) {
         if (!toffs[(size_t)i]) continue;
         ebbkc_graph* g = b->graphs[(size_t)i];
         hipLaunchKernelGGL(k_btask_fill, dim3(gridn(seeds_of(g))), dim3(256), 0, s, sizes_of(g), seeds_of(g),
-                           b->ks[(size_t)i] - 2, log_thr, toffs[(size_t)i], gbase[(size_t)i], (int32_t)i, tasks, tg,
-                           keys, vals);
+                           b->ks[(size_t)i] - 2, log_thr, toffs[(size_t)i], gbase[(size_t)i], (int32_t)i, gbits, tasks,
+                           tg, keys, vals);
     }
-    CHKB(radix_sort_u64(keys, vals, keys2, vals2, total, 10, hist, htmp, s));
+    CHKB(radix_sort_u64(keys, vals, keys2, vals2, total, 10 + gbits, hist, htmp, s));
     CHKB(dev_alloc(b, (void**)&b->tasks, sizeof(int64_t) * total, s));
     CHKB(dev_alloc(b, (void**)&b->tgraph, sizeof(int32_t) * total, s));
     hipLaunchKernelGGL(k_bgather, dim3(gridn(total)), dim3(256), 0, s, tasks, tg, vals, total, b->tasks, b->tgraph);
     CHKB(hipMemsetAsync(b->ctr, 0, 16 * sizeof(unsigned long long), s));
-    hipLaunchKernelGGL(k_bclass_hist, dim3(gridn(total)), dim3(256), 0, s, keys, total, b->ctr);
+    hipLaunchKernelGGL(k_bclass_hist, dim3(gridn(total)), dim3(256), 0, s, keys, total, gbits, b->ctr);
     unsigned long long cc[4];
     CHKB(hipMemcpyAsync(cc, b->ctr, sizeof(cc), hipMemcpyDeviceToHost, s));
     CHKB(hipStreamSynchronize(s));
@@ -371,7 +386,10 @@ ebbkc_status finish(ebbkc_batch* b, uint64_t* out, ebbkc_status* status = nullpt
 }
 
 std::mutex g_tune_mu;
-std::map<std::string, std::pair<int32_t, int32_t>> g_tune_cache;
+struct Tuned {
+    int32_t split, bpc, node_split;
+};
+std::map<std::string, Tuned> g_tune_cache;
 
 std::string signature(const ebbkc_batch* b) {
     // graphs, total seeds (log2 bucket), k histogram
@@ -382,7 +400,8 @@ std::string signature(const ebbkc_batch* b) {
         hist[std::min(15, (int)b->ks[i])]++;
     }
     char buf[256];
-    int o = snprintf(buf, sizeof(buf), "n%zu_s%d", b->graphs.size(), seeds > 0 ? (int)std::log2((double)seeds) : 0);
+    int o = snprintf(buf, sizeof(buf), "n%zu_s%d%s", b->graphs.size(), seeds > 0 ? (int)std::log2((double)seeds) : 0,
+                     b->build ? "_build" : "");
     for (int k = 3; k < 16; ++k)
         if (hist[k]) o += snprintf(buf + o, sizeof(buf) - (size_t)o, "_k%d:%d", k, hist[k]);
     return std::string(buf);
@@ -394,8 +413,8 @@ void load_cache_file() {
     FILE* f = fopen(path, "r");
     if (!f) return;
     char key[256];
-    int a, c;
-    while (fscanf(f, "%255s %d %d", key, &a, &c) == 3) g_tune_cache[key] = {a, c};
+    int a, c, d;
+    while (fscanf(f, "%255s %d %d %d", key, &a, &c, &d) == 4) g_tune_cache[key] = {a, c, d};
     fclose(f);
 }
 
@@ -404,7 +423,8 @@ void save_cache_file() {
     if (!path) return;
     FILE* f = fopen(path, "w");
     if (!f) return;
-    for (auto& kv : g_tune_cache) fprintf(f, "%s %d %d\n", kv.first.c_str(), kv.second.first, kv.second.second);
+    for (auto& kv : g_tune_cache)
+        fprintf(f, "%s %d %d %d\n", kv.first.c_str(), kv.second.split, kv.second.bpc, kv.second.node_split);
     fclose(f);
 }
 
@@ -513,7 +533,9 @@ ebbkc_status batch_create_impl(ebbkc_graph* const* graphs, const int32_t* ks, in
     if (dev_alloc(b, (void**)&b->gtau, sizeof(int32_t) * n, s) != hipSuccess) return fail(EBBKC_E_OOM);
     if (dev_alloc(b, (void**)&b->gtot, sizeof(unsigned long long) * 2 * n, s) != hipSuccess) return fail(EBBKC_E_OOM);
     if (dev_alloc(b, (void**)&b->ctr, sizeof(unsigned long long) * 16, s) != hipSuccess) return fail(EBBKC_E_OOM);
-    if (b->opt.node_split != -1 && b->opt.blocks_per_cu != -1) {
+    // the split queue (a few MB): always for a batch of its own, whose tuner
+    // may turn splitting on; for a served epoch only when its options use it
+    if (!async_mem || (b->opt.node_split != -1 && b->opt.blocks_per_cu != -1)) {
         if (dev_alloc(b, (void**)&b->squeue, sizeof(SplitItem) * SQ_CAP, s) != hipSuccess ||
             dev_alloc(b, (void**)&b->sq, sizeof(unsigned long long) * SQ_WORDS, s) != hipSuccess)
             return fail(EBBKC_E_OOM);
@@ -542,8 +564,9 @@ ebbkc_status batch_create_impl(ebbkc_graph* const* graphs, const int32_t* ks, in
         if (g_tune_cache.empty()) load_cache_file();
         auto it = g_tune_cache.find(signature(b));
         if (it != g_tune_cache.end() && !opt) {
-            b->opt.split_threshold = it->second.first;
-            b->opt.blocks_per_cu = it->second.second;
+            b->opt.split_threshold = it->second.split;
+            b->opt.blocks_per_cu = it->second.bpc;
+            b->opt.node_split = it->second.node_split;
         }
     }
     ebbkc_status st = build_tasks(b, s);
@@ -584,39 +607,55 @@ ebbkc_status ebbkc_batch_run(ebbkc_batch* b, int32_t use_graph, uint64_t* out_co
     return finish(b, out_counts);
 }
 
-ebbkc_status ebbkc_batch_tune(ebbkc_batch* b, void* stream, int32_t* out_split, int32_t* out_blocks_per_cu) {
+ebbkc_status ebbkc_batch_tune(ebbkc_batch* b, void* stream, int32_t* out_split, int32_t* out_blocks_per_cu,
+                              int32_t* out_node_split) {
     if (!b) return EBBKC_E_INVALID_ARG;
     hipStream_t s = (hipStream_t)stream;
-    const int32_t splits[] = {1 << 16, 1 << 22, 1 << 28, -1};
+    // tasks that build their g_i are one per seed whatever the threshold
+    const std::vector<int32_t> splits = b->build ? std::vector<int32_t>{b->opt.split_threshold}
+                                                 : std::vector<int32_t>{1 << 16, 1 << 22, 1 << 28, -1};
     const int32_t bpcs[] = {0, 1, 2, -1};
+    const int32_t nsplits[] = {-1, 1 << 10, 0, 1 << 22};  // off, shallow .. deep only (0: 2^16)
     double best = 1e300;
-    int32_t bs = b->opt.split_threshold, bb = b->opt.blocks_per_cu;
+    int32_t bs = b->opt.split_threshold, bb = b->opt.blocks_per_cu, bn = b->opt.node_split;
     std::vector<uint64_t> ref(b->graphs.size()), cur(b->graphs.size());
     bool have_ref = false;
+    auto trial = [&](int32_t sp, int32_t bp, int32_t ns) -> ebbkc_status {
+        b->opt.blocks_per_cu = bp;
+        b->opt.node_split = ns;
+        b->dirty = true;
+        ebbkc_status st = ebbkc_batch_run(b, 0, cur.data(), stream);
+        if (st) return st;
+        if (!have_ref) { ref = cur; have_ref = true; }
+        else if (cur != ref) return EBBKC_E_HIP;  // every setting must give the same counts
+        if (b->last_ms < best) { best = b->last_ms; bs = sp; bb = bp; bn = ns; }
+        return EBBKC_OK;
+    };
+    const int32_t ns0 = b->opt.node_split;
     for (int32_t sp : splits) {
         b->opt.split_threshold = sp;
         ebbkc_status st = build_tasks(b, s);
         if (st) return st;
-        for (int32_t bp : bpcs) {
-            b->opt.blocks_per_cu = bp;
-            st = ebbkc_batch_run(b, 0, cur.data(), stream);
-            if (st) return st;
-            if (!have_ref) { ref = cur; have_ref = true; }
-            else if (cur != ref) return EBBKC_E_HIP;  // every setting must give the same counts
-            if (b->last_ms < best) { best = b->last_ms; bs = sp; bb = bp; }
-        }
+        for (int32_t bp : bpcs)
+            if ((st = trial(sp, bp, ns0))) return st;
     }
     b->opt.split_threshold = bs;
-    b->opt.blocks_per_cu = bb;
     ebbkc_status st = build_tasks(b, s);
     if (st) return st;
+    if (bb != -1)  // the split queue needs persistent grids
+        for (int32_t ns : nsplits)
+            if (ns != ns0 && (st = trial(bs, bb, ns))) return st;
+    b->opt.blocks_per_cu = bb;
+    b->opt.node_split = bn;
+    b->dirty = true;
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
-        g_tune_cache[signature(b)] = {bs, bb};
+        g_tune_cache[signature(b)] = {bs, bb, bn};
         save_cache_file();
     }
     if (out_split) *out_split = bs;
     if (out_blocks_per_cu) *out_blocks_per_cu = bb;
+    if (out_node_split) *out_node_split = bn;
     return EBBKC_OK;
 }
 

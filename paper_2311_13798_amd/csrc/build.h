@@ -9,10 +9,14 @@
 //                  after r) is scanned; each entry is looked up in the other
 //                  endpoint's id-sorted row, whose rank must also exceed r.
 //   2. sub-graph   E(g_i): pairs of V(g_i) joined by an edge ranked after r.
-//                  Every member's degree-oriented row prefix ranked after r
-//                  is scanned (all members' prefixes flattened over the
-//                  wave's lanes) against an LDS hash of V(g_i); each such
-//                  edge is met exactly once.
+//                  With an adjacency bitmap of G (small graphs), every pair
+//                  of members is tested directly (one bit, and for an edge
+//                  its rank found from the bitmap's cumulative counts): about
+//                  c^2 / 2 tests, against about c times the out-degree for a
+//                  scan.  Otherwise every member's degree-oriented row prefix
+//                  ranked after r is scanned (all members' prefixes flattened
+//                  over the wave's lanes) against an LDS hash of V(g_i); each
+//                  such edge is met exactly once.  Both give the same rows.
 //   3. colouring   greedy colouring (colours 1, 2, ...) visiting vertices by
 //                  non-increasing degree in g_i, ties to the smaller vertex
 //                  id (Section 4.3; Algorithm EBBkC-H colours each g_i).
@@ -77,6 +81,21 @@ __device__ __forceinline__ int hash_find(const BuildScratch<W>& S, int32_t key) 
     return -1;
 }
 
+// Whether (x, w) is an edge of G ranked after r: a bit of the adjacency
+// bitmap, then the edge's rank at its position in the id-sorted row (the
+// entries before its word plus the set bits below it in the word); without
+// a bitmap, by binary search of the id-sorted row.
+__device__ __forceinline__ bool later_edge(const GraphView& G, int32_t x, int32_t w, int32_t r) {
+    if (G.adj) {
+        const int64_t o = (int64_t)x * G.adjw + (w >> 6);
+        const uint64_t word = G.adj[o];
+        if (!((word >> (w & 63)) & 1)) return false;
+        return G.erank[G.rp[x] + (int)G.acum[o] + popc64(word & ((1ull << (w & 63)) - 1))] > r;
+    }
+    const int q = lower_bound_i32(G.ci, G.rp[x], G.rp[x + 1], w);
+    return q < G.rp[x + 1] && G.ci[q] == w && G.erank[q] > r;
+}
+
 // number of entries of row x (rank-sorted, descending) ranked after r
 __device__ __forceinline__ int prefix_after(const int32_t* __restrict__ rp, const int2* __restrict__ rrow, int32_t x,
                                             int32_t r) {
@@ -113,8 +132,7 @@ __device__ int build_subbranch(const GraphView& G, int32_t u, int32_t v, int32_t
         int32_t w = -1;
         if (idx < lx) {
             w = G.rrow[G.rp[xs] + idx].x;
-            const int q = lower_bound_i32(G.ci, G.rp[ys], G.rp[ys + 1], w);
-            ok = q < G.rp[ys + 1] && G.ci[q] == w && G.erank[q] > r;
+            ok = later_edge(G, ys, w, r);
         }
         const uint64_t mk = ballot(ok);
         if (ok) {
@@ -127,61 +145,77 @@ __device__ int build_subbranch(const GraphView& G, int32_t u, int32_t v, int32_t
     if (c > CAP || (expect >= 0 && c != expect)) return -1;
 
     // ---- 2. sub-graph bitmap
-    for (int j = lane; j < HS; j += 64) S.hkey[j] = -1;
     for (int i = lane; i < c; i += 64)
 #pragma unroll
         for (int w = 0; w < W; ++w) rows[i][w] = 0;
-    wave_sync();
-    for (int i = lane; i < c; i += 64) {
-        const int32_t key = S.gid[i];
-        uint32_t h = hslot(key, HS);
-        while (true) {
-            const int32_t old = atomicCAS(&S.hkey[h], -1, key);
-            if (old == -1) { S.hval[h] = (int16_t)i; break; }
-            h = (h + 1) & (HS - 1);
-        }
-    }
-    wave_sync();
-    {
-        int plen[W];
-#pragma unroll
-        for (int q = 0; q < W; ++q) {
-            const int i = lane + 64 * q;
-            plen[q] = 0;
-            if (i < c) {
-                const int32_t w = S.gid[i];
-                int lo = G.orp[w], hi = G.orp[w + 1];
-                const int base = lo;
-                while (lo < hi) {
-                    int mid = (lo + hi) >> 1;
-                    if (G.orow[mid].y > r) lo = mid + 1; else hi = mid;
+    if (G.adj) {
+        wave_sync();
+        const int U = c * (c - 1) / 2;
+        for (int u0 = 0; u0 < U; u0 += 64) {
+            const int u = u0 + lane;
+            if (u < U) {
+                int i, j;
+                upper_pair(u, c, i, j);
+                if (later_edge(G, S.gid[i], S.gid[j], r)) {
+                    atomicOr((unsigned long long*)&rows[i][j >> 6], 1ull << (j & 63));
+                    atomicOr((unsigned long long*)&rows[j][i >> 6], 1ull << (i & 63));
                 }
-                plen[q] = lo - base;
             }
         }
-        int total = 0;
-#pragma unroll
-        for (int q = 0; q < W; ++q) {
-            const int inc = wave_incl_scan(plen[q]);
-            const int i = lane + 64 * q;
-            if (i < c) S.key[i] = total + inc - plen[q];
-            total += __shfl(inc, 63, 64);
+    } else {
+        for (int j = lane; j < HS; j += 64) S.hkey[j] = -1;
+        wave_sync();
+        for (int i = lane; i < c; i += 64) {
+            const int32_t key = S.gid[i];
+            uint32_t h = hslot(key, HS);
+            while (true) {
+                const int32_t old = atomicCAS(&S.hkey[h], -1, key);
+                if (old == -1) { S.hval[h] = (int16_t)i; break; }
+                h = (h + 1) & (HS - 1);
+            }
         }
         wave_sync();
-        for (int base = 0; base < total; base += 64) {
-            const int j = base + lane;
-            if (j < total) {
-                int lo = 0, hi = c;  // last member whose offset is <= j
-                while (hi - lo > 1) {
-                    int mid = (lo + hi) >> 1;
-                    if (S.key[mid] <= j) lo = mid; else hi = mid;
+        {
+            int plen[W];
+#pragma unroll
+            for (int q = 0; q < W; ++q) {
+                const int i = lane + 64 * q;
+                plen[q] = 0;
+                if (i < c) {
+                    const int32_t w = S.gid[i];
+                    int lo = G.orp[w], hi = G.orp[w + 1];
+                    const int base = lo;
+                    while (lo < hi) {
+                        int mid = (lo + hi) >> 1;
+                        if (G.orow[mid].y > r) lo = mid + 1; else hi = mid;
+                    }
+                    plen[q] = lo - base;
                 }
-                const int i = lo;
-                const int2 yr = G.orow[G.orp[S.gid[i]] + (j - S.key[i])];
-                const int jj = hash_find(S, yr.x);
-                if (jj >= 0) {
-                    atomicOr((unsigned long long*)&rows[i][jj >> 6], 1ull << (jj & 63));
-                    atomicOr((unsigned long long*)&rows[jj][i >> 6], 1ull << (i & 63));
+            }
+            int total = 0;
+#pragma unroll
+            for (int q = 0; q < W; ++q) {
+                const int inc = wave_incl_scan(plen[q]);
+                const int i = lane + 64 * q;
+                if (i < c) S.key[i] = total + inc - plen[q];
+                total += __shfl(inc, 63, 64);
+            }
+            wave_sync();
+            for (int base = 0; base < total; base += 64) {
+                const int j = base + lane;
+                if (j < total) {
+                    int lo = 0, hi = c;  // last member whose offset is <= j
+                    while (hi - lo > 1) {
+                        int mid = (lo + hi) >> 1;
+                        if (S.key[mid] <= j) lo = mid; else hi = mid;
+                    }
+                    const int i = lo;
+                    const int2 yr = G.orow[G.orp[S.gid[i]] + (j - S.key[i])];
+                    const int jj = hash_find(S, yr.x);
+                    if (jj >= 0) {
+                        atomicOr((unsigned long long*)&rows[i][jj >> 6], 1ull << (jj & 63));
+                        atomicOr((unsigned long long*)&rows[jj][i >> 6], 1ull << (i & 63));
+                    }
                 }
             }
         }

@@ -53,7 +53,8 @@ int opts_of(const ebbkc_options& o) {
 constexpr int CNT_WORDS = 64;
 
 GraphView graph_view(const ebbkc_graph* g) {
-    return GraphView{g->rp, g->ci, g->erank, g->rrow, g->orp, g->orow, g->eu, g->ev, g->rank};
+    return GraphView{g->rp, g->ci, g->erank, g->rrow, g->orp, g->orow, g->eu, g->ev, g->rank,
+                     g->adj, g->acum, g->adjw};
 }
 
 __host__ __device__ inline int width_of(int c) { return c <= 64 ? 1 : (c <= 128 ? 2 : (c <= 192 ? 3 : 4)); }

@@ -63,6 +63,19 @@ __device__ __forceinline__ uint64_t upper_mask(int x, int w) {
     return xb == 63 ? 0ull : (~0ull << (xb + 1));
 }
 
+// Pair u of the r(r-1)/2 pairs (i, j), i < j < r, numbered row by row (row i
+// starts at i (2r - i - 1) / 2): the row from the quadratic's root, then
+// corrected by whole rows against float rounding.
+__device__ __forceinline__ void upper_pair(int u, int r, int& i, int& j) {
+    const float R2 = 2.0f * (float)r - 1.0f;
+    int ii = (int)((R2 - sqrtf(R2 * R2 - 8.0f * (float)u)) * 0.5f);
+    ii = ii < 0 ? 0 : (ii > r - 2 ? r - 2 : ii);
+    while (ii < r - 2 && (ii + 1) * (2 * r - ii - 2) / 2 <= u) ++ii;
+    while (ii > 0 && ii * (2 * r - ii - 1) / 2 > u) --ii;
+    i = ii;
+    j = u - ii * (2 * r - ii - 1) / 2 + ii + 1;
+}
+
 template <int W>
 __device__ __forceinline__ int popcW(const uint64_t (&p)[W]) {
     int c = 0;

@@ -52,6 +52,11 @@ struct ebbkc_graph {
     int32_t* orp = nullptr;   // n+1
     int2* orow = nullptr;     // m
     int32_t* byrank = nullptr; // m: edge id at each rank
+    // adjacency bitmap (n <= the adjacency bound): n rows of adjw words, and
+    // per word the entries of the id-sorted row below it
+    uint64_t* adj = nullptr;
+    uint16_t* acum = nullptr;
+    int32_t adjw = 0;
     int32_t* subsize = nullptr; // m: |V(g_i)| per edge (filled on demand)
     int32_t* vpos = nullptr;    // n: position in the root vertex order (orderings COLOR, DEGEN_VERTEX)
     int32_t* vcol = nullptr;    // n: greedy colour of G (ordering COLOR)

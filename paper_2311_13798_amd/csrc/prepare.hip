@@ -19,6 +19,7 @@
 #include <chrono>
 #include <vector>
 
+#include "arena.h"
 #include "common.h"
 #include "device_util.h"
 #include "handle.h"
@@ -291,6 +292,31 @@ __global__ void k_gather_rrow(const uint32_t* __restrict__ perm, const int32_t* 
 __global__ void k_byrank(const int32_t* __restrict__ rank, int64_t m, int32_t* __restrict__ byrank) {
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (int64_t)gridDim.x * blockDim.x)
         byrank[rank[e]] = (int32_t)e;
+}
+
+// adjacency bitmap: one bit per CSR entry (a row's entries may share a word)
+__global__ void k_adj_fill(const int32_t* __restrict__ src, const int32_t* __restrict__ ci, int64_t nnz, int32_t aw,
+                           uint64_t* __restrict__ adj) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nnz; i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t w = ci[i];
+        atomicOr((unsigned long long*)&adj[(int64_t)src[i] * aw + (w >> 6)], 1ull << (w & 63));
+    }
+}
+
+// acum[x aw + q] = entries of x's id-sorted row below vertex 64 q
+__global__ void k_adj_cum(const int32_t* __restrict__ rp, const int32_t* __restrict__ ci, int32_t n, int32_t aw,
+                          uint16_t* __restrict__ acum) {
+    const int64_t total = (int64_t)n * aw;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t x = (int32_t)(t / aw), q = (int32_t)(t % aw);
+        int lo = rp[x], hi = rp[x + 1];
+        const int base = lo;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (ci[mid] < 64 * q) lo = mid + 1; else hi = mid;
+        }
+        acum[t] = (uint16_t)(lo - base);
+    }
 }
 
 // ---- vertex orders for the root edge order of the ablation orderings
@@ -717,6 +743,19 @@ ebbkc_status prepare_impl(ebbkc_graph* g, const int32_t* row_ptr, const int32_t*
     if (m) {
         hipLaunchKernelGGL(k_byrank, dim3(grid_for(m)), dim3(TB), 0, s, rank.p, m, byrank.p);
     }
+    // ---- adjacency bitmap for sub-branch builds by pair tests (small graphs)
+    DBuf<uint64_t> adj;
+    DBuf<uint16_t> acum;
+    const int32_t amax = g->opt.adj_max_n == 0 ? ADJ_DEFAULT_MAX_N : g->opt.adj_max_n;
+    const int32_t aw = (n + 63) / 64;
+    const bool with_adj = amax > 0 && n > 0 && n <= amax && m > 0;
+    if (with_adj) {
+        CHK(adj.alloc((int64_t)n * aw));
+        CHK(acum.alloc((int64_t)n * aw));
+        CHK(hipMemsetAsync(adj.p, 0, sizeof(uint64_t) * (size_t)n * aw, s));
+        hipLaunchKernelGGL(k_adj_fill, dim3(grid_for(nnz)), dim3(TB), 0, s, src.p, ci.p, nnz, aw, adj.p);
+        hipLaunchKernelGGL(k_adj_cum, dim3(grid_for((int64_t)n * aw)), dim3(TB), 0, s, rp.p, ci.p, n, aw, acum.p);
+    }
     CHK(hipGetLastError());
     CHK(hipEventRecord(ev1, s));
     CHK(hipStreamSynchronize(s));
@@ -738,8 +777,14 @@ ebbkc_status prepare_impl(ebbkc_graph* g, const int32_t* row_ptr, const int32_t*
     g->orp = orp.release();
     g->orow = orow.release();
     g->byrank = byrank.release();
+    if (with_adj) {
+        g->adj = adj.release();
+        g->acum = acum.release();
+        g->adjw = aw;
+    }
     g->device_bytes = (int64_t)sizeof(int32_t) * ((n + 1) * 2 + nnz * 2 + m * 6) + (int64_t)sizeof(int2) * (nnz + m) +
-                      (int64_t)sizeof(int32_t) * n * ((g->vpos ? 1 : 0) + (g->vcol ? 1 : 0));
+                      (int64_t)sizeof(int32_t) * n * ((g->vpos ? 1 : 0) + (g->vcol ? 1 : 0)) +
+                      (with_adj ? (int64_t)n * aw * (int64_t)(sizeof(uint64_t) + sizeof(uint16_t)) : 0);
     return EBBKC_OK;
 }
 

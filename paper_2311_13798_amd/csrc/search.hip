@@ -17,6 +17,8 @@
 //     (Section 4.3, Algorithm EBBkC-C).
 // Nodes with l = 4 or 5 hand their children (l = 2 or 3) to lanes, one child
 // per lane; everything above is wave-uniform with the lanes owning rows.
+#include <type_traits>
+
 #include "arena.h"
 #include "build.h"
 #include "device_util.h"
@@ -160,13 +162,72 @@ struct SearchMem {
     int16_t vl[64 * W];      // that set's vertices in order, one per lane
     int32_t pq[2][QCAP];     // queued children |Q| << 16 | x << 8 | y (and a sort buffer)
     Frame<W> fr[LDS_FRAMES];
+    // a node's candidate set renumbered onto W - 1 words (compact_set, W = 2
+    // and 3): rows of up to 64 (W - 1) vertices, and their colours
+    uint64_t crow[W == 2 || W == 3 ? 64 * (W - 1) * (W - 1) : 1];
+    int16_t ccol[W == 2 || W == 3 ? 64 * (W - 1) : 1];
 };
+
+// nodes with fewer candidates are not renumbered onto narrower rows
+constexpr int COMPACT_MIN = 32;
+
+// The p vertices of P (p <= 64 WV, WV < W) renumbered 0 .. p-1 in ascending
+// order, with their rows restricted to P and renumbered likewise (WV words)
+// and their colours.  The order is kept, so the DAG (lower index first), the
+// colour order and every clique inside P are the same; the node's leaves
+// then run on WV-word rows.
+template <int W, int WV>
+__device__ void compact_set(const SearchMem<W>& M, const uint64_t (&P)[W], uint64_t (*rows_out)[WV],
+                            int16_t* col_out) {
+    const int lane = lane_id();
+    int base = 0;
+#pragma unroll
+    for (int q = 0; q < W; ++q) {
+        if (!P[q]) continue;
+        if ((P[q] >> lane) & 1) {
+            const int v = 64 * q + lane;
+            const int idx = base + popc64(P[q] & lanemask_lt());
+            uint64_t nr[WV];
+#pragma unroll
+            for (int z = 0; z < WV; ++z) nr[z] = 0;
+            uint64_t cur = 0;
+            int t = 0;
+#pragma unroll
+            for (int qq = 0; qq < W; ++qq) {
+                const uint64_t rw = M.rows[v][qq];
+                uint64_t bq = P[qq];
+                while (bq) {
+                    const int b = __builtin_ctzll(bq);
+                    bq &= bq - 1;
+                    cur |= ((rw >> b) & 1ull) << (t & 63);
+                    if ((t & 63) == 63) {
+#pragma unroll
+                        for (int z = 0; z < WV; ++z)
+                            if (z == (t >> 6)) nr[z] = cur;
+                        cur = 0;
+                    }
+                    ++t;
+                }
+            }
+            if (t & 63) {
+#pragma unroll
+                for (int z = 0; z < WV; ++z)
+                    if (z == (t >> 6)) nr[z] = cur;
+            }
+#pragma unroll
+            for (int z = 0; z < WV; ++z) rows_out[idx][z] = nr[z];
+            col_out[idx] = M.col[v];
+        }
+        base += popc64(P[q]);
+    }
+    wave_sync();
+}
 
 // ---------------------------------------------------------------- per-lane leaves
 // One lane counts the cliques of one child candidate set Q from LDS rows.
 
 template <int W>
-__device__ __forceinline__ uint64_t lane_edges(const SearchMem<W>& M, const uint64_t (&Q)[W]) {
+__device__ __forceinline__ uint64_t lane_edges(const uint64_t (*rows)[W], const uint64_t (&Q)[W]) {
     uint32_t e2 = 0;
 #pragma unroll
     for (int wz = 0; wz < W; ++wz) {
@@ -175,7 +236,7 @@ __device__ __forceinline__ uint64_t lane_edges(const SearchMem<W>& M, const uint
             const int z = wz * 64 + __builtin_ctzll(bits);
             bits &= bits - 1;
 #pragma unroll
-            for (int w = 0; w < W; ++w) e2 += popc64(Q[w] & M.rows[z][w]);
+            for (int w = 0; w < W; ++w) e2 += popc64(Q[w] & rows[z][w]);
         }
     }
     return e2 / 2;
@@ -189,7 +250,7 @@ __device__ __forceinline__ uint64_t lane_edges(const SearchMem<W>& M, const uint
 // back to the sparse pass if Q turns out sparse after all; otherwise the
 // degrees come first and only the needed pass follows.
 template <int W>
-__device__ __forceinline__ uint64_t lane_triangles(const SearchMem<W>& M, const uint64_t (&Q)[W], bool dense_hint,
+__device__ __forceinline__ uint64_t lane_triangles(const uint64_t (*rows)[W], const uint64_t (&Q)[W], bool dense_hint,
                                                    uint64_t& ops) {
     constexpr int H = 2 * W;  // 32-bit halves of a row
     const int q = popcW(Q);
@@ -210,7 +271,7 @@ __device__ __forceinline__ uint64_t lane_triangles(const SearchMem<W>& M, const 
             while (bits) {
                 const int b = __builtin_ctz(bits);
                 bits &= bits - 1;
-                const uint32_t* rz = reinterpret_cast<const uint32_t*>(M.rows[32 * hz + b]);
+                const uint32_t* rz = reinterpret_cast<const uint32_t*>(rows[32 * hz + b]);
                 uint32_t Cz[H];  // missing pairs z-y inside Q with y > z
                 int d = 0;
 #pragma unroll
@@ -227,7 +288,7 @@ __device__ __forceinline__ uint64_t lane_triangles(const SearchMem<W>& M, const 
 #pragma unroll
                 for (int gy = hz; gy < H; ++gy) {
                     while (Cz[gy]) {
-                        const uint32_t* ry = reinterpret_cast<const uint32_t*>(M.rows[32 * gy + __builtin_ctz(Cz[gy])]);
+                        const uint32_t* ry = reinterpret_cast<const uint32_t*>(rows[32 * gy + __builtin_ctz(Cz[gy])]);
                         Cz[gy] &= Cz[gy] - 1;
 #pragma unroll
                         for (int g = gy; g < H; ++g) t += __builtin_popcount(Cz[g] & ~ry[g]);
@@ -252,7 +313,7 @@ __device__ __forceinline__ uint64_t lane_triangles(const SearchMem<W>& M, const 
                 bits &= bits - 1;
                 int d = 0;
 #pragma unroll
-                for (int w = 0; w < W; ++w) d += popc64(Q[w] & M.rows[z][w]);
+                for (int w = 0; w < W; ++w) d += popc64(Q[w] & rows[z][w]);
                 e2 += d;
                 const int cm = q - 1 - d;
                 s2 += (uint32_t)(cm * (cm - 1) / 2);
@@ -273,7 +334,7 @@ __device__ __forceinline__ uint64_t lane_triangles(const SearchMem<W>& M, const 
             uint64_t Cz[W];  // missing (dense) or present (sparse) pairs z-y, y > z, inside Q
 #pragma unroll
             for (int w = 0; w < W; ++w) {
-                const uint64_t row = dense ? ~M.rows[z][w] : M.rows[z][w];
+                const uint64_t row = dense ? ~rows[z][w] : rows[z][w];
                 Cz[w] = Q[w] & row & upper_mask(z, w);
             }
 #pragma unroll
@@ -283,7 +344,7 @@ __device__ __forceinline__ uint64_t lane_triangles(const SearchMem<W>& M, const 
                     Cz[wy] &= Cz[wy] - 1;
 #pragma unroll
                     for (int w = 0; w < W; ++w) {
-                        const uint64_t row = dense ? ~M.rows[y][w] : M.rows[y][w];
+                        const uint64_t row = dense ? ~rows[y][w] : rows[y][w];
                         if (w >= wy) t += popc64(Cz[w] & row);
                     }
                 }
@@ -581,10 +642,18 @@ __device__ __forceinline__ unsigned long long sq_load(unsigned long long* p) {
 __device__ __forceinline__ unsigned long long sq_add(unsigned long long* p, long long v) {
     return __hip_atomic_fetch_add(p, (unsigned long long)v, __ATOMIC_SEQ_CST, __HIP_MEMORY_SCOPE_AGENT);
 }
-// longest time a wave waits without work before it gives up with ERR_QUEUE
-// (constant-rate clock of 100 MHz: 60 s), far above any single queued node;
-// also at most SQ_WAIT_SPINS sleeps (each at least 64 * 32 clocks), so the
-// wait ends even if that clock did not advance
+// a hint only (whether to push): no ordering, no wait for the wave's other
+// memory operations
+__device__ __forceinline__ unsigned long long sq_peek(unsigned long long* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+constexpr int SQ_POLL_BUSY = 256, SQ_POLL_HUNGRY = 4;
+constexpr uint64_t SQ_POLL_TICKS = 2000;  // 20 us of the 100 MHz clock
+// longest time a wave waits while the queue shows no progress (no item
+// claimed or reserved, no change in the working waves) before it gives up
+// with ERR_QUEUE (constant-rate clock of 100 MHz: 60 s); also at most
+// SQ_WAIT_SPINS sleeps (each at least 64 * 32 clocks), so the wait ends even
+// if that clock did not advance
 constexpr uint64_t SQ_WAIT_TICKS = 6000000000ull;
 constexpr uint64_t SQ_WAIT_SPINS = 1ull << 26;
 
@@ -594,21 +663,35 @@ constexpr uint64_t SQ_WAIT_SPINS = 1ull << 26;
 // that wave stops counting as working) or after SQ_WAIT_TICKS without work
 // (ERR_QUEUE).  A claim takes the head first and counts the wave as working
 // after it; a wave in between may process that node while others have
-// finished, and handles whatever it pushes itself.  Idle polling backs off.
+// finished, and handles whatever it pushes itself.  Idle polling backs off
+// and reads the counters without ordering (an ordered atomic would also
+// drop the compute unit's vector cache, which the working waves beside it
+// use for their spilled registers); only a claim and the final check that
+// nothing is left are ordered.
 __device__ int64_t queue_take(const SearchArgs& a) {
     unsigned long long* sq = a.sq;
-    const uint64_t t0 = wall_clock64();
+    uint64_t t0 = wall_clock64();
+    unsigned long long seen_h = ~0ull, seen_r = ~0ull, seen_b = ~0ull;
     int nap = 1;
     for (uint64_t spin = 0;; ++spin) {
         long long got = -1;
         int done = 0;
         if (lane_id() == 0) {
-            const unsigned long long h = sq_load(&sq[SQ_HEAD]), r = sq_load(&sq[SQ_RESERVE]);
+            const unsigned long long h = sq_peek(&sq[SQ_HEAD]), r = sq_peek(&sq[SQ_RESERVE]);
+            const unsigned long long bz = sq_peek(&sq[SQ_BUSY]);
+            if (h != seen_h || r != seen_r || bz != seen_b) {  // progress: the wait starts again
+                seen_h = h;
+                seen_r = r;
+                seen_b = bz;
+                t0 = wall_clock64();
+                spin = 0;
+            }
             if (h < r && atomicCAS(&sq[SQ_HEAD], h, h + 1) == h) {
                 got = (long long)h;
                 sq_add(&sq[SQ_BUSY], 1);
                 sq_add(&sq[SQ_IDLE], -1);
-            } else if (h >= r && sq_load(&sq[SQ_BUSY]) == 0 && sq_load(&sq[SQ_HEAD]) >= sq_load(&sq[SQ_RESERVE])) {
+            } else if (h >= r && bz == 0 && sq_load(&sq[SQ_BUSY]) == 0 &&
+                       sq_load(&sq[SQ_HEAD]) >= sq_load(&sq[SQ_RESERVE])) {
                 done = 1;
             } else if (wall_clock64() - t0 > SQ_WAIT_TICKS || spin > SQ_WAIT_SPINS) {
                 atomicOr(a.err, ERR_QUEUE);
@@ -635,7 +718,7 @@ __device__ int64_t queue_take(const SearchArgs& a) {
         }
         if (done) return -1;
         for (int i = 0; i < nap; ++i) __builtin_amdgcn_s_sleep(64);
-        nap = nap < 16 ? 2 * nap : 16;
+        nap = nap < 32 ? 2 * nap : 32;
     }
 }
 
@@ -664,6 +747,24 @@ __global__ __launch_bounds__(256, (W <= 2 ? 4 : (W <= 3 ? 3 : 2))) void k_search
     const bool splitting = a.squeue != nullptr;
     if (splitting && lane == 0) sq_add(&a.sq[SQ_BUSY], 1);
     bool on_queue = false, took_item = false;
+    int poll_in = 0;      // candidate nodes until the queue counters are read again
+    uint64_t poll_t = 0;  // when they were read last
+    bool hungry = false;  // some wave waited for work at the last reading
+    // lane j: the least |P| with C(|P|, j) >= split_bound (a node with l = j
+    // and fewer candidates is never handed over), so that the test per node
+    // is a lane read instead of a table load
+    int push_pmin = 1 << 20;
+    if (splitting) {
+        const int j = lane;
+        int lo = j > 0 ? j : 1, hi = 64 * MAX_W + 1;  // C(hi, j) may stay below the bound: then never
+        if (j > 0 && binom(hi, j) >= a.split_bound) {
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (binom(mid, j) >= a.split_bound) hi = mid; else lo = mid + 1;
+            }
+            push_pmin = lo;
+        }
+    }
 
     for (;;) {
         unsigned long long it = 0;
@@ -864,128 +965,159 @@ __global__ __launch_bounds__(256, (W <= 2 ? 4 : (W <= 3 ? 3 : 2))) void k_search
         // 4-cliques inside R (r >= 4 vertices) from the missing pairs H of R:
         // inclusion-exclusion over the edge sets of H spanning at most four
         // vertices gives K4 = C(r,4) - M C(r-2,2) + P3 (r-3) + 2K2 - T (r-3)
-        // - P4 - S3 + C4 + paw - diamond + K4(H), with M the missing pairs,
-        // P3 the 2-paths, 2K2 the disjoint pairs, T the triangles, P4 the
-        // 3-paths, S3 the 3-stars, C4 the 4-cycles, paw, diamond and K4(H)
-        // the remaining 4-vertex shapes of H.  With m_v the missing pairs at v
-        // and c(a,b) the common H-neighbours of a and b: P3 = sum C(m_v,2),
-        // S3 = sum C(m_v,3), 2K2 = C(M,2) - P3, and over the pairs of R,
-        // C4 = sum C(c,2) / 2, and over the missing pairs, 3T = sum c,
-        // diamond = sum C(c,2), P4 = sum (m_a-1)(m_b-1) - 3T, paw = sum c
-        // (m_a + m_b - 4) / 2, K4(H) by the H-edges among the common
-        // H-neighbours above b.  The pairs of R are spread evenly over the
-        // lanes (pair index -> (i, j) in closed form), so the work does not
-        // pile up on the vertices with many missing pairs.  Returns false,
-        // counting nothing, when branching on R costs less.
-        auto k4_missing = [&](const uint64_t (&R)[W], int r, bool whole, int64_t& S, uint64_t& uacc,
+        // - P4 - S3 + C4 + paw - diamond + K4(H), with P3 the 2-paths, 2K2
+        // the disjoint pairs, T the triangles, P4 the 3-paths, S3 the 3-stars,
+        // C4 the 4-cycles, paw, diamond and K4(H) the remaining 4-vertex
+        // shapes of H.  All but C(r,4) + C(M,2) is a sum over the vertices,
+        // missing pairs and 2-paths of H, taken by the lanes holding them
+        // into S (12 times its value, so that every term is an integer).
+        // Returns false, counting nothing, when H is too dense for this to
+        // beat branching on the pairs of R.  (Spreading all pairs of R over
+        // the lanes instead evens out vertices with many missing pairs, but
+        // costs ~r^2 / 64 rounds even for a nearly complete R; on R-MAT s18
+        // at k = 9 it made the search 1.7x slower.)
+        auto k4_missing = [&](auto wv, const auto& R, auto rows, int r, bool whole, int64_t& S, uint64_t& uacc,
                               bool& rdense) -> bool {
-            (void)S;
-            // the vertices of R, packed onto consecutive lanes (ascending)
+            constexpr int WV = decltype(wv)::value;
+            // the vertices of R, packed onto consecutive lanes
             {
                 int base = 0;
 #pragma unroll
-                for (int q = 0; q < W; ++q) {
+                for (int q = 0; q < WV; ++q) {
                     if ((R[q] >> lane) & 1) M.vl[base + popc64(R[q] & lanemask_lt())] = (int16_t)(lane + 64 * q);
                     base += popc64(R[q]);
                 }
             }
             wave_sync();
             const int rounds = (r + 63) >> 6;
-            uint32_t msum = 0, cm2 = 0, cm3 = 0;
+            int msum = 0, cm2 = 0, lw = 0;
             for (int t = 0; t < rounds; ++t) {
                 const int j = 64 * t + lane;
                 if (j < r) {
                     const int v = M.vl[j];
                     int mv = -1;  // R & ~row(v) holds v itself
 #pragma unroll
-                    for (int w = 0; w < W; ++w) mv += popc64(R[w] & ~M.rows[v][w]);
+                    for (int w = 0; w < WV; ++w) mv += popc64(R[w] & ~rows[v][w]);
                     M.md[v] = (int16_t)mv;
-                    msum += (uint32_t)mv;
-                    cm2 += (uint32_t)(mv * (mv - 1) / 2);
-                    cm3 += (uint32_t)(mv * (mv - 1) * (mv - 2) / 6);
+                    msum += mv;
+                    cm2 += mv * (mv - 1) / 2;
+                    lw += mv + mv * (mv - 1) / 2;
                 }
             }
-            const int64_t Msum = (int64_t)wsum_u32(msum);
+            const int Msum = (int)wsum_u32((uint32_t)msum);
+            const int64_t P3 = (int64_t)wsum_u32((uint32_t)cm2);
+            // The lanes run in lockstep, so this evaluation takes as long as
+            // its busiest lane (missing pairs + 2-paths at the vertices it
+            // holds, ~15 instructions each) plus ~150 for the reductions.  The
+            // alternative for one R = P & N+(x) of an l = 5 node is one child
+            // y per lane counting the triangles of R & N+(y): ~35 instructions
+            // per vertex of the largest child, ~ r * d, per 64 children (r of
+            // them here, sharing rounds with the other x through the queue);
+            // for a whole l = 4 node it is that for every x (~18 instructions
+            // a step), ~ |E(R)| * d / 64 rounds of 64 children.
+            const int lmax = wmax_i32(lw);
             const float pairs = 0.5f * (float)r * (float)(r - 1);
             const float E = pairs - 0.5f * (float)Msum, d = E / pairs;
             rdense = 2.0f * E >= pairs;
-            // cost: ~45 instructions per pair of R over 64 lanes, ~150 for the
-            // reductions; the alternative for one R = P & N+(x) of an l = 5
-            // node is one child y per lane counting the triangles of
-            // R & N+(y) (~35 instructions per vertex of the child, ~ r d, per
-            // 64 children); for a whole l = 4 node it is that for every x
-            // (~18 instructions a step, ~ |E(R)| d / 64 rounds)
-            const float cost = a.k4_weight * (45.0f * pairs / 64.0f + 150.0f);
+            const float cost = a.k4_weight * (15.0f * (float)lmax + 150.0f);
             const float alt = whole ? 18.0f * E * d * (float)r * d / 64.0f
                                     : 35.0f * (float)r * d * (float)r / 64.0f;
             if (!(a.k4_weight > 0.f) || cost > alt) return false;
-            const int64_t P3 = (int64_t)wsum_u32(cm2), S3 = (int64_t)wsum_u32(cm3);
-            const int64_t Mh = Msum / 2, rr = r;
-            const int64_t base4 = rr * (rr - 1) * (rr - 2) * (rr - 3) / 24;
-            if (work) wk_ops += (uint64_t)r * W;
-            if (Mh == 0) {
-                uacc += (uint64_t)base4;
-                return true;
-            }
+            if (work) wk_ops += (uint64_t)(r + Msum + P3) * WV;
+            const int64_t Mh = Msum / 2;
+            const uint64_t r64 = (uint64_t)r;
+            uacc += r64 * (r64 - 1) * (r64 - 2) * (r64 - 3) / 24 + (uint64_t)(Mh * (Mh - 1) / 2);
+            if (Msum == 0) return true;
             wave_sync();  // md[] of every vertex of R
-            const int U = r * (r - 1) / 2;
-            const float R2 = 2.0f * (float)r - 1.0f;
-            uint64_t c4 = 0, t3 = 0, dia = 0, p4 = 0, paw = 0, kk = 0;
-            for (int u0 = 0; u0 < U; u0 += 64) {
-                const int u = u0 + lane;
-                if (u >= U) continue;
-                // row i of the upper triangle starts at i (2r - i - 1) / 2
-                int i = (int)((R2 - sqrtf(R2 * R2 - 8.0f * (float)u)) * 0.5f);
-                i = i < 0 ? 0 : (i > r - 2 ? r - 2 : i);
-                while (i < r - 2 && (i + 1) * (2 * r - i - 2) / 2 <= u) ++i;
-                while (i > 0 && i * (2 * r - i - 1) / 2 > u) --i;
-                const int j = u - i * (2 * r - i - 1) / 2 + i + 1;
-                const int va = M.vl[i], vb = M.vl[j];
-                uint64_t ra[W], X[W];
-                int un = 0;
-                bool e = false;
+            const int64_t c2 = (int64_t)(r - 2) * (r - 3) / 2;
+            for (int t = 0; t < rounds; ++t) {
+                const int j = 64 * t + lane;
+                if (j >= r) continue;
+                const int v = M.vl[j];
+                uint64_t hv[WV];
 #pragma unroll
-                for (int w = 0; w < W; ++w) {
-                    ra[w] = M.rows[va][w];
-                    X[w] = R[w] & ~(ra[w] | M.rows[vb][w]);
-                    un += popc64(X[w]);
-                    if (w == (vb >> 6)) e = !((ra[w] >> (vb & 63)) & 1);
-                }
-                // X holds va and vb themselves exactly when they miss each other
-                const int c = un - (e ? 2 : 0);
-                c4 += (uint64_t)(c * (c - 1) / 2);
-                if (e) {
-                    const int ma = M.md[va], mb = M.md[vb];
-                    t3 += (uint64_t)c;
-                    dia += (uint64_t)(c * (c - 1) / 2);
-                    p4 += (uint64_t)((ma - 1) * (mb - 1));
-                    paw += (uint64_t)(c * (ma + mb - 4));
-                    if (c >= 2) {  // K4(H) through (va, vb): H-edges among the common H-neighbours above vb
+                for (int w = 0; w < WV; ++w)
+                    hv[w] = R[w] & ~rows[v][w] & (w == (v >> 6) ? ~(1ull << (v & 63)) : ~0ull);
+                const int64_t mv = M.md[v];
+                if (mv == 0) continue;
+                S += -6 * c2 * mv + 12 * (int64_t)(r - 4) * (mv * (mv - 1) / 2) - 2 * mv * (mv - 1) * (mv - 2);
+                // missing pairs v-u: codegree cc in H (triangles, diamonds,
+                // paws), the 3-paths through v-u, K4(H).  Per-v sums in 32 bits:
+                // t2 = sum cc over all u; over u > v: a1 = sum cc, a2 = sum cc^2,
+                // a3 = sum (m_u - 1)
+                int32_t t2 = 0, a1 = 0, a2 = 0, a3 = 0;
 #pragma unroll
-                        for (int w = 0; w < W; ++w) X[w] &= upper_mask(vb, w);
+                for (int wu = 0; wu < WV; ++wu) {
+                    uint64_t bu = hv[wu];
+                    while (bu) {
+                        const int u = wu * 64 + __builtin_ctzll(bu);
+                        bu &= bu - 1;
+                        uint64_t hu[WV];
 #pragma unroll
-                        for (int wz = 0; wz < W; ++wz) {
-                            uint64_t bz = X[wz];
-                            while (bz) {
-                                const int z = 64 * wz + __builtin_ctzll(bz);
-                                bz &= bz - 1;
-                                int hz = 0;
+                        for (int w = 0; w < WV; ++w) hu[w] = R[w] & ~rows[u][w];
+                        int cc = -1;  // u lies in both hv and hu
 #pragma unroll
-                                for (int w = 0; w < W; ++w)
-                                    if (w >= wz) hz += popc64(X[w] & ~M.rows[z][w] & upper_mask(z, w));
-                                kk += (uint64_t)hz;
+                        for (int w = 0; w < WV; ++w) cc += popc64(hv[w] & hu[w]);
+                        t2 += cc;
+                        if (u > v) {
+                            a1 += cc;
+                            a2 += cc * cc;
+                            a3 += M.md[u] - 1;
+                            if (cc >= 2) {
+                                uint64_t X[WV];
+#pragma unroll
+                                for (int w = 0; w < WV; ++w) X[w] = hv[w] & hu[w] & upper_mask(u, w);
+#pragma unroll
+                                for (int wx = 0; wx < WV; ++wx) {
+                                    while (X[wx]) {
+                                        const int z = wx * 64 + __builtin_ctzll(X[wx]);
+                                        X[wx] &= X[wx] - 1;
+                                        int kk = 0;
+#pragma unroll
+                                        for (int w = 0; w < WV; ++w)
+                                            if (w >= wx) kk += popc64(X[w] & ~rows[z][w]);
+                                        S += 12 * kk;
+                                    }
+                                }
                             }
                         }
                     }
                 }
+                // per missing pair: 12 (cc - (m_u-1)(m_v-1)) - 4 (r-3) cc - 6 cc (cc-1)
+                S += (int64_t)(18 - 4 * (r - 3)) * a1 - 6 * (int64_t)a2 - 12 * (mv - 1) * (int64_t)a3 +
+                     6 * (int64_t)t2 * (mv - 2);
+                // 2-paths a-v-b (a < b): 4 C4 = sum (codeg(a,b) - 1); with
+                // ha = R & ~row(a), |ha & ~row(b)| = codeg(a,b) + 2 [a-b missing]
+                int32_t wsum = 0;
+#pragma unroll
+                for (int wa = 0; wa < WV; ++wa) {
+                    uint64_t ba = hv[wa];
+                    while (ba) {
+                        const int a0 = wa * 64 + __builtin_ctzll(ba);
+                        ba &= ba - 1;
+                        uint64_t ha[WV], rest[WV];
+                        int corr = 0;
+#pragma unroll
+                        for (int w = 0; w < WV; ++w) {
+                            ha[w] = R[w] & ~rows[a0][w];
+                            rest[w] = hv[w] & upper_mask(a0, w);
+                            corr += 2 * popc64(rest[w] & ha[w]) + popc64(rest[w]);
+                        }
+                        wsum -= corr;
+#pragma unroll
+                        for (int wb = 0; wb < WV; ++wb) {
+                            if (wb < wa) continue;
+                            while (rest[wb]) {
+                                const int b = wb * 64 + __builtin_ctzll(rest[wb]);
+                                rest[wb] &= rest[wb] - 1;
+#pragma unroll
+                                for (int w = 0; w < WV; ++w) wsum += popc64(ha[w] & ~rows[b][w]);
+                            }
+                        }
+                    }
+                }
+                S += 3 * (int64_t)wsum;
             }
-            if (work) wk_ops += (uint64_t)U * W;
-            const int64_t C4 = (int64_t)wave_sum(c4) / 2, T3 = (int64_t)wave_sum(t3);
-            const int64_t DIA = (int64_t)wave_sum(dia), P4 = (int64_t)wave_sum(p4) - T3;
-            const int64_t PAW = (int64_t)wave_sum(paw) / 2, K4H = (int64_t)wave_sum(kk);
-            const int64_t k4 = base4 - Mh * ((rr - 2) * (rr - 3) / 2) + P3 * (rr - 3) + (Mh * (Mh - 1) / 2 - P3) -
-                               (T3 / 3) * (rr - 3) - P4 - S3 + C4 + PAW - DIA + K4H;
-            uacc += (uint64_t)k4;
             return true;
         };
 
@@ -994,7 +1126,9 @@ __global__ __launch_bounds__(256, (W <= 2 ? 4 : (W <= 3 ? 3 : 2))) void k_search
         // counted by the wave from its missing pairs; otherwise its children
         // (x, y) join a queue in LDS and every 64 queued children are counted
         // one per lane.
-        auto children_by_lanes = [&](const uint64_t (&P)[W], int l, int xlo, int xhi) {
+        auto children_by_lanes = [&](auto wv, const auto& P, auto rows, const int16_t* col, int cn, int l, int xlo,
+                                     int xhi) {
+            constexpr int WV = decltype(wv)::value;
             uint64_t lsum = 0, lops = 0, usum = 0;
             int64_t S = 0;
             const int lc = l - 2;
@@ -1004,11 +1138,11 @@ __global__ __launch_bounds__(256, (W <= 2 ? 4 : (W <= 3 ? 3 : 2))) void k_search
                 if (lane < cnt) {
                     const int e = q[base + lane];
                     const int x = (e >> 8) & 0xFF, y = e & 0xFF;
-                    uint64_t Q[W];
+                    uint64_t Q[WV];
 #pragma unroll
-                    for (int w = 0; w < W; ++w) Q[w] = P[w] & M.rows[x][w] & M.rows[y][w] & upper_mask(y, w);
-                    if (lc == 3) lsum += lane_triangles(M, Q, (e >> 25) & 1, lops);
-                    else lsum += lane_edges(M, Q);
+                    for (int w = 0; w < WV; ++w) Q[w] = P[w] & rows[x][w] & rows[y][w] & upper_mask(y, w);
+                    if (lc == 3) lsum += lane_triangles<WV>(rows, Q, (e >> 25) & 1, lops);
+                    else lsum += lane_edges<WV>(rows, Q);
                 }
             };
             // Count every queued child: a lane's work grows with |Q|, so the
@@ -1046,38 +1180,38 @@ __global__ __launch_bounds__(256, (W <= 2 ? 4 : (W <= 3 ? 3 : 2))) void k_search
                 wave_sync();
             };
             bool done = false;
-            if (l == 4 && xlo == 0 && xhi >= c) {
+            if (l == 4 && xlo == 0 && xhi >= cn) {
                 const int pc = popcW(P);
                 bool pd = false;
-                done = pc < 4 || k4_missing(P, pc, true, S, usum, pd);
+                done = pc < 4 || k4_missing(wv, P, rows, pc, true, S, usum, pd);
             }
             int xx = xlo - 1;
             while (!done) {
                 int nx = -1;
 #pragma unroll
-                for (int w = W - 1; w >= 0; --w) {
+                for (int w = WV - 1; w >= 0; --w) {
                     const uint64_t b = P[w] & (xx < 0 ? ~0ull : upper_mask(xx, w));
                     if (b) nx = w * 64 + __builtin_ctzll(b);
                 }
-                if (nx < 0 || nx >= xhi || (rule1 && M.col[nx] < l)) break;
+                if (nx < 0 || nx >= xhi || (rule1 && col[nx] < l)) break;
                 xx = nx;
-                uint64_t Rx[W];
+                uint64_t Rx[WV];
 #pragma unroll
-                for (int w = 0; w < W; ++w) Rx[w] = uni64(P[w] & M.rows[xx][w] & upper_mask(xx, w));
+                for (int w = 0; w < WV; ++w) Rx[w] = uni64(P[w] & rows[xx][w] & upper_mask(xx, w));
                 const int rc = popcW(Rx);
                 if (rc < lc + 1) continue;
-                if (work) { wk_nodes += rc; wk_ops += (uint64_t)rc * W; }
+                if (work) { wk_nodes += rc; wk_ops += (uint64_t)rc * WV; }
                 bool rdense = false;
-                if (l == 5 && k4_missing(Rx, rc, false, S, usum, rdense)) continue;
+                if (l == 5 && k4_missing(wv, Rx, rows, rc, false, S, usum, rdense)) continue;
 #pragma unroll
-                for (int q = 0; q < W; ++q) {
+                for (int q = 0; q < WV; ++q) {
                     const int y = 64 * q + lane;
-                    const bool act = ((Rx[q] >> lane) & 1) && !(rule1 && M.col[y] < l - 1);
+                    const bool act = ((Rx[q] >> lane) & 1) && !(rule1 && col[y] < l - 1);
                     const uint64_t bq = ballot(act);
                     if (act) {
                         int qy = 0;  // |Q| of the child (x, y)
 #pragma unroll
-                        for (int w = 0; w < W; ++w) qy += popc64(Rx[w] & M.rows[y][w] & upper_mask(y, w));
+                        for (int w = 0; w < WV; ++w) qy += popc64(Rx[w] & rows[y][w] & upper_mask(y, w));
                         M.pq[0][qn + popc64(bq & lanemask_lt())] = (rdense ? 1 << 25 : 0) | (qy << 16) | (xx << 8) | y;
                     }
                     qn += popc64(bq);
@@ -1088,6 +1222,28 @@ __global__ __launch_bounds__(256, (W <= 2 ? 4 : (W <= 3 ? 3 : 2))) void k_search
             if (work) wk_ops += wave_sum(lops);
             const int64_t s12 = wave_sum(S);
             tacc.add((uint64_t)((int64_t)(wave_sum(lsum) + usum) + s12 / 12));
+        };
+
+        // Children of a node with l = 4 or 5 (x in [xlo, xhi)).  Classes
+        // W = 2 and 3 first renumber a whole node whose candidate set fits
+        // W - 1 words onto them (one narrower instance of the children and
+        // leaf code per class keeps the kernel's spill space small), unless
+        // the node is so small that renumbering (~6 W |P| instructions)
+        // costs more than the narrower words save.
+        auto count_children = [&](const uint64_t (&Pn)[W], int ln, int xlo, int xhi) {
+            if constexpr (W == 2 || W == 3) {
+                constexpr int WN = W - 1;
+                const int p = popcW(Pn);
+                if (xlo == 0 && xhi >= c && p <= 64 * WN && p >= COMPACT_MIN) {
+                    uint64_t (*cr)[WN] = reinterpret_cast<uint64_t (*)[WN]>(M.crow);
+                    compact_set<W, WN>(M, Pn, cr, M.ccol);
+                    uint64_t Pc[WN];
+                    prefix_mask<WN>(p, Pc);
+                    children_by_lanes(std::integral_constant<int, WN>{}, Pc, cr, M.ccol, p, ln, 0, 64 * WN);
+                    return;
+                }
+            }
+            children_by_lanes(std::integral_constant<int, W>{}, Pn, M.rows, M.col, c, ln, xlo, xhi);
         };
 
         const int l0 = k - 2;
@@ -1106,7 +1262,7 @@ __global__ __launch_bounds__(256, (W <= 2 ? 4 : (W <= 3 ? 3 : 2))) void k_search
                 uint64_t Pn[W];
 #pragma unroll
                 for (int w = 0; w < W; ++w) Pn[w] = uni64(a.squeue[qitem].P[w]);
-                children_by_lanes(Pn, lq, 0, c);
+                count_children(Pn, lq, 0, c);
                 active = false;
             }
         } else if (whole) {
@@ -1155,20 +1311,41 @@ __global__ __launch_bounds__(256, (W <= 2 ? 4 : (W <= 3 ? 3 : 2))) void k_search
             }
         }
         if (active && qitem < 0 && (l0 == 4 || l0 == 5)) {
-            children_by_lanes(P0, l0, x0, x1);
+            count_children(P0, l0, x0, x1);
             active = false;
         }
         // hand node (Pn, ln), ln >= 4, to an idle wave through the queue
         // instead of searching it here; true when it was pushed
+        // Whether waves wait for work is read from the counters (relaxed
+        // loads, a round trip to L2) only every SQ_POLL_BUSY candidate nodes
+        // while none wait and every SQ_POLL_HUNGRY while some do, and at
+        // least every SQ_POLL_TICKS; in between the last answer stands.
         auto try_push = [&](const uint64_t (&Pn)[W], int ln) -> bool {
             if (!splitting || ln < 4) return false;
-            if (binom(popcW(Pn), ln) < a.split_bound) return false;
+            const int pn = popcW(Pn);
+            if (ln < 64 ? pn < __builtin_amdgcn_readlane(push_pmin, ln) : binom(pn, ln) < a.split_bound) return false;
+            if (a.split_mode != SPLIT_FORCED) {
+                if (poll_in > 0 && wall_clock64() - poll_t < SQ_POLL_TICKS) {
+                    --poll_in;
+                    if (!hungry) return false;
+                } else {
+                    poll_t = wall_clock64();
+                    int hg = 0;
+                    if (lane == 0) {
+                        unsigned long long* sq = a.sq;
+                        const unsigned long long r = sq_peek(&sq[SQ_RESERVE]), h = sq_peek(&sq[SQ_HEAD]);
+                        hg = sq_peek(&sq[SQ_IDLE]) > r - h;
+                    }
+                    hungry = uniform_i32(__shfl(hg, 0, 64)) != 0;
+                    poll_in = hungry ? SQ_POLL_HUNGRY : SQ_POLL_BUSY;
+                    if (!hungry) return false;
+                }
+            }
             int ok = 0;
             if (lane == 0) {
                 unsigned long long* sq = a.sq;
-                const unsigned long long r = sq_load(&sq[SQ_RESERVE]), h = sq_load(&sq[SQ_HEAD]);
-                const bool want = a.split_mode == SPLIT_FORCED || sq_load(&sq[SQ_IDLE]) > r - h;
-                if (want && r + SQ_SLACK < (unsigned long long)SQ_CAP) {
+                const unsigned long long r = sq_peek(&sq[SQ_RESERVE]);
+                if (r + SQ_SLACK < (unsigned long long)SQ_CAP) {
                     const unsigned long long si = sq_add(&sq[SQ_RESERVE], 1);
                     SplitItem& I = a.squeue[si];
                     I.it = (int64_t)it;
@@ -1261,7 +1438,7 @@ __global__ __launch_bounds__(256, (W <= 2 ? 4 : (W <= 3 ? 3 : 2))) void k_search
             u128 v = 0;
             if (finish(Pc, lc, v)) { tacc.add(v); continue; }
             if (try_push(Pc, lc)) continue;
-            if (lc == 4 || lc == 5) { children_by_lanes(Pc, lc, 0, c); continue; }
+            if (lc == 4 || lc == 5) { count_children(Pc, lc, 0, c); continue; }
             if (sp >= LDS_FRAMES + (gfr ? GLOBAL_FRAMES : 0)) {
                 if (lane == 0) atomicOr(a.err, ERR_DEPTH);
                 continue;

@@ -35,11 +35,7 @@ __global__ void k_subsize(GraphView G, int64_t m, int32_t* __restrict__ out) {
         for (int base = 0; base < lx; base += 64) {
             const int idx = base + lane;
             bool ok = false;
-            if (idx < lx) {
-                const int32_t w = G.rrow[G.rp[xs] + idx].x;
-                const int q = lower_bound_i32(G.ci, G.rp[ys], G.rp[ys + 1], w);
-                ok = q < G.rp[ys + 1] && G.ci[q] == w && G.erank[q] > r;
-            }
+            if (idx < lx) ok = later_edge(G, ys, G.rrow[G.rp[xs] + idx].x, r);
             c += popc64(ballot(ok));
         }
         if (lane == 0) out[e] = c;

@@ -63,7 +63,8 @@ def test_batch_with_split_heavy_roots_and_tuning(ebb):
     o.split_threshold = 500
     B = ebb.Batch(Gs, ks, options=o)
     assert B.run(use_graph=True) == want
-    split, bpc = B.tune()
+    split, bpc, node_split = B.tune()
+    assert node_split in (-1, 1 << 10, 0, 1 << 22)
     assert B.run(use_graph=True) == want
     assert B.run(use_graph=False) == want
     B.close()
@@ -75,7 +76,8 @@ def test_batch_with_split_heavy_roots_and_tuning(ebb):
 def test_batch_tasks_that_build_their_own_subbranch(ebb, ordering):
     # batch_build = BUILD: no arena; every task builds its g_i in LDS from the graph's arrays
     # (the form for batches whose arenas would not fit device memory).  Same counts as the oracle
-    # and as the arena form, eagerly and on HIP-graph replays, with heavy roots split into ranges.
+    # and as the arena form, eagerly and on HIP-graph replays (one task per seed when tasks build;
+    # heavy roots split into ranges in the arena form).
     gs = mixed_graphs(count=40, seed=11)
     gs += [(graphgen.er_planted(300, 0.05, 1, 40, 40, seed=s), k) for s, k in zip(range(4), (6, 8, 10, 7))]
     gs += [(graphgen.er_planted(180, 0.55, 0, 2, 2, seed=21), 7), (graphgen.complete(70), 20)]
