@@ -129,12 +129,14 @@ typedef struct {
     int32_t node_split;        /* runtime splitting of search nodes over waves through a device
                                   queue (root sub-branches and their subtrees are independent,
                                   Section 6.2 (7)): 0 (default): a node with l >= 4 and at least
-                                  2^16 l-subsets is handed to a waiting wave while some wave waits
+                                  2^20 l-subsets is handed to a waiting wave while some wave waits
                                   for work; n >= 2: the same with n l-subsets; 1: every node with
                                   l >= 4 is handed over while the queue has room (exercises the
                                   queue at every depth); -1: off.  Not used by listings, per-seed
-                                  counts, EBBkC-T or non-persistent launches (blocks_per_cu = -1).
-                                  Counts are the same. */
+                                  counts, EBBkC-T, non-persistent launches (blocks_per_cu = -1)
+                                  or served epochs (they run concurrently, and waves waiting for
+                                  nodes would hold compute units the other epochs need).  Counts
+                                  are the same. */
     int32_t adj_max_n;         /* sub-branch builds (Eq. edge-oriented-branching: the edges among
                                   V(g_i) ranked after e_i): graphs with at most this many vertices
                                   get an adjacency bitmap of G at prepare (n^2 / 8 bytes plus a

@@ -133,6 +133,11 @@ enum : int { SQ_HEAD = 0, SQ_RESERVE = 16, SQ_BUSY = 32, SQ_IDLE = 48, SQ_PUSHED
 constexpr int64_t SQ_CAP = 1 << 16;        // items per launch
 constexpr int64_t SQ_SLACK = 1 << 13;       // more than the waves of one launch
 constexpr int SPLIT_OFF = 0, SPLIT_ON_DEMAND = 1, SPLIT_FORCED = 2;
+// default bound of runtime splitting: a node is handed over only if it has at
+// least this many l-subsets (2^16 pushed so many small nodes that the queue
+// filled early and its round trips cost more than they saved; 2^20 was best
+// on R-MAT s12/s13 and Chung-Lu 3e5 at k = 11, 12)
+constexpr uint64_t NODE_SPLIT_DEFAULT = 1ull << 20;
 
 // A graph whose sub-branches are built by the search tasks themselves (no
 // arena): its arrays, |V(g_i)| of every edge, and the colours of G kept in

@@ -323,11 +323,14 @@ ebbkc_status enqueue(ebbkc_batch* b, hipStream_t s) {
         a.work = b->ctr + 8;
         a.err = (int*)(b->ctr + 6);
         a.gframes = b->gframes;
-        if (b->squeue && b->opt.node_split != -1 && b->opt.blocks_per_cu != -1) {  // persistent grids only
+        // persistent grids only; not in served epochs, which run concurrently
+        // (waves waiting for split nodes would hold compute units that the
+        // other epochs need)
+        if (b->squeue && !b->async_mem && b->opt.node_split != -1 && b->opt.blocks_per_cu != -1) {
             a.squeue = b->squeue;
             a.sq = b->sq;
             a.split_mode = b->opt.node_split == 1 ? SPLIT_FORCED : SPLIT_ON_DEMAND;
-            a.split_bound = b->opt.node_split == 1 ? 0 : (b->opt.node_split >= 2 ? (uint64_t)b->opt.node_split : 1ull << 16);
+            a.split_bound = b->opt.node_split == 1 ? 0 : (b->opt.node_split >= 2 ? (uint64_t)b->opt.node_split : NODE_SPLIT_DEFAULT);
             CHKB(launch_sq_reset(b->sq, b->squeue, s));
         }
         CHKB(launch_search(W, b->build, a, b->cu_count, b->opt.blocks_per_cu, s));
@@ -533,9 +536,9 @@ ebbkc_status batch_create_impl(ebbkc_graph* const* graphs, const int32_t* ks, in
     if (dev_alloc(b, (void**)&b->gtau, sizeof(int32_t) * n, s) != hipSuccess) return fail(EBBKC_E_OOM);
     if (dev_alloc(b, (void**)&b->gtot, sizeof(unsigned long long) * 2 * n, s) != hipSuccess) return fail(EBBKC_E_OOM);
     if (dev_alloc(b, (void**)&b->ctr, sizeof(unsigned long long) * 16, s) != hipSuccess) return fail(EBBKC_E_OOM);
-    // the split queue (a few MB): always for a batch of its own, whose tuner
-    // may turn splitting on; for a served epoch only when its options use it
-    if (!async_mem || (b->opt.node_split != -1 && b->opt.blocks_per_cu != -1)) {
+    // the split queue (a few MB) for a batch of its own (served epochs do not
+    // split nodes at run time)
+    if (!async_mem) {
         if (dev_alloc(b, (void**)&b->squeue, sizeof(SplitItem) * SQ_CAP, s) != hipSuccess ||
             dev_alloc(b, (void**)&b->sq, sizeof(unsigned long long) * SQ_WORDS, s) != hipSuccess)
             return fail(EBBKC_E_OOM);
@@ -615,7 +618,7 @@ ebbkc_status ebbkc_batch_tune(ebbkc_batch* b, void* stream, int32_t* out_split, 
     const std::vector<int32_t> splits = b->build ? std::vector<int32_t>{b->opt.split_threshold}
                                                  : std::vector<int32_t>{1 << 16, 1 << 22, 1 << 28, -1};
     const int32_t bpcs[] = {0, 1, 2, -1};
-    const int32_t nsplits[] = {-1, 1 << 10, 0, 1 << 22};  // off, shallow .. deep only (0: 2^16)
+    const int32_t nsplits[] = {-1, 1 << 16, 0, 1 << 24};  // off, small nodes too .. large ones only (0: 2^20)
     double best = 1e300;
     int32_t bs = b->opt.split_threshold, bb = b->opt.blocks_per_cu, bn = b->opt.node_split;
     std::vector<uint64_t> ref(b->graphs.size()), cur(b->graphs.size());

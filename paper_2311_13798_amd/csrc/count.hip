@@ -618,7 +618,7 @@ static ebbkc_status run_tasks(ebbkc_graph* g, int32_t k, const int64_t* tsorted,
             a.squeue = squeue;
             a.sq = sq;
             a.split_mode = g->opt.node_split == 1 ? SPLIT_FORCED : SPLIT_ON_DEMAND;
-            a.split_bound = g->opt.node_split == 1 ? 0 : (g->opt.node_split >= 2 ? (uint64_t)g->opt.node_split : 1ull << 16);
+            a.split_bound = g->opt.node_split == 1 ? 0 : (g->opt.node_split >= 2 ? (uint64_t)g->opt.node_split : NODE_SPLIT_DEFAULT);
             CHKH(launch_sq_reset(sq, squeue, s));
         }
         if (g->opt.count_work && !list && !truss) a.wave_time = (unsigned long long*)(g->d_counters + 32 + 4 * (W - 1));

@@ -64,7 +64,7 @@ def test_batch_with_split_heavy_roots_and_tuning(ebb):
     B = ebb.Batch(Gs, ks, options=o)
     assert B.run(use_graph=True) == want
     split, bpc, node_split = B.tune()
-    assert node_split in (-1, 1 << 10, 0, 1 << 22)
+    assert node_split in (-1, 1 << 16, 0, 1 << 24)
     assert B.run(use_graph=True) == want
     assert B.run(use_graph=False) == want
     B.close()
