@@ -297,7 +297,7 @@ def batch_full(ebb, torch, configs, count=4096, threads=16):
     return out
 
 
-def served_full(ebb, torch, configs, rates=(50, 100, 200, 500, 1000, 2000), count=2000, cap_s=1.0,
+def served_full(ebb, torch, configs, rates=(50, 100, 200, 500, 1000, 2000), count=500, cap_s=1.0,
                 budget=1 << 36):
     """The served workload at its stated shape: a resident catalogue of R-MAT s12..s18, Chung-Lu
     n = 1e4, 3e4, 1e5, 3e5, 1e6 (200 n / 1e6 planted cliques, at least 2), ER(2000, 0.01) and the first
@@ -495,6 +495,7 @@ def main():
                     help="only the batched workload at its stated size (4,096 graphs), plain vs fused")
     ap.add_argument("--served-full", action="store_true",
                     help="only the served workload at its stated shape (full catalogue, six rates)")
+    ap.add_argument("--served-count", type=int, default=500, help="requests per rate in --served-full")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU sharding of this "
@@ -521,7 +522,7 @@ def main():
         import paper_2311_13798_amd as ebb
         from graphgen import configs
         torch.cuda.set_device(0)
-        print(json.dumps({"served_full": served_full(ebb, torch, configs)}), flush=True)
+        print(json.dumps({"served_full": served_full(ebb, torch, configs, count=args.served_count)}), flush=True)
         return
     ks = [int(x) for x in args.ks.split(",") if x]
 
