@@ -169,7 +169,7 @@ struct SearchMem {
 };
 
 // nodes with fewer candidates are not renumbered onto narrower rows
-constexpr int COMPACT_MIN = 32;
+constexpr int COMPACT_MIN = 16;
 
 // The p vertices of P (p <= 64 WV, WV < W) renumbered 0 .. p-1 in ascending
 // order, with their rows restricted to P and renumbered likewise (WV words)
