@@ -159,3 +159,25 @@ def test_chunked_listing_equals_the_whole_listing(ebb):
         assert total == c and ghu == hu and nch == len(sizes)
         assert np.array_equal(allt[np.lexsort(allt.T[::-1])], ref)
     G.close()
+
+
+def test_deep_listing_of_two_overlapping_cliques(ebb):
+    # two K_35 sharing 30 vertices: a seed in the shared part has 38 candidates with 25 missing pairs
+    # (not a t-plex for t <= 3), so counts and listings at k = 31..36 branch deeper than the frames
+    # kept in LDS and use the device-memory frames.  N_k = 2 C(35, k) - C(30, k).
+    import itertools
+    from math import comb
+    A, B = range(0, 35), range(5, 40)
+    edges = sorted({(a, b) for S in (A, B) for a, b in itertools.combinations(S, 2)})
+    g = graphgen.from_edges(40, edges)
+    G = ebb.Graph.from_csr(g)
+    for k in (31, 33, 34, 35, 36):
+        want = 2 * comb(35, k) - comb(30, k)
+        print(f"case deep list k={k} n={want}", flush=True)
+        assert G.count(k) == want == oracle.count(g, k)
+        c, ho, hu, ref = oracle.list_lex(g, k)
+        w, gho, ghu, tup = gpu_list(ebb, G, k)
+        assert w == c == want
+        assert (gho, ghu) == (ho, hu)
+        assert np.array_equal(tup, ref)
+    G.close()
