@@ -81,12 +81,23 @@ def left(budget_s):
 
 # ---------------------------------------------------------------- HBM traffic record
 
-def source_sha256() -> str:
-    """Hash of the search kernel's sources (the traffic record is valid only for these)."""
+def code_of(text: str) -> str:
+    """C++ source without comments and blank space: what the compiler sees of it."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
+def source_sha256(read=None) -> str:
+    """Hash of the search kernel's code, comments left out (the traffic record is valid only for
+    this code).  read(name) gives a file's text (default: the file under csrc/)."""
+    if read is None:
+        def read(name):
+            with open(os.path.join(CSRC, name), encoding="utf-8") as fh:
+                return fh.read()
     h = hashlib.sha256()
-    for f in ("search.hip", "arena.h", "device_util.h", "common.h"):
-        with open(os.path.join(CSRC, f), "rb") as fh:
-            h.update(fh.read())
+    for f in ("search.hip", "build.h", "arena.h", "device_util.h", "common.h"):
+        h.update(code_of(read(f)).encode())
     return h.hexdigest()
 
 

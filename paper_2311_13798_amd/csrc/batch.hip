@@ -1,12 +1,16 @@
 // batch.hip -- many (graph, k) counts in one fused launch per bitmap width
 // class, captured once in a HIP graph and replayed.
 //
-// Every graph of the batch is prepared and has its sub-branch arena; the
-// tasks of all graphs (as in a single count: one per seed with enough
-// vertices, heavy roots split per first vertex) are merged into one list,
-// sorted by width class and then by the vertices a task can still use,
-// largest first, so the persistent waves of one launch draw work from every
-// graph.  Each task adds its count to its own graph's exact 128-bit total.
+// Every graph of the batch is prepared; its sub-branches come from its arena
+// or, for batches whose arenas would not fit device memory, are built by
+// each task in LDS.  The tasks of all graphs (as in a single count: one per
+// seed with enough vertices, heavy roots split per first vertex when the
+// sub-branches come from arenas) are merged into one list, sorted by width
+// class and then by the vertices a task can still use, largest first (tasks
+// that build: by graph first, so a launch works on one graph's arrays at a
+// time), so the persistent waves of one launch draw work from every graph.
+// Each task adds its count to its own graph's exact 128-bit total; a served
+// epoch is such a batch, without runtime node splitting.
 //
 // Autotuning: ebbkc_batch_tune times the batch under a few (split threshold,
 // workgroups per CU) settings, then, with the best of those, a few bounds for

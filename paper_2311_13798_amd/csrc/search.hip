@@ -1,9 +1,11 @@
 // search.hip -- the EBBkC-C_Rec search over arena sub-branches (one
 // wavefront per task).
 //
-// A task is a seed's g_i (from the arena) and a range [x0, x1) of first
-// vertices of the root's children; light seeds are one task, heavy seeds one
-// task per root vertex.  On the DAG of g_i (vertices in colour order, edges
+// A task is a seed's g_i (from the arena, or built in LDS by the task) and a
+// range [x0, x1) of first vertices of the root's children; light seeds are
+// one task, heavy seeds one task per range of root vertices.  While some
+// waves wait for work, a node can also be handed to one of them through a
+// device queue.  On the DAG of g_i (vertices in colour order, edges
 // low -> high) a node (P, l):
 //   * is pruned when |P| < l (Algorithm EBBkC);
 //   * at l = 1 counts |P|, at l = 2 the edges inside P;
@@ -16,7 +18,8 @@
 //     (col x < l or col y < l-1) and Rule (2) (fewer than l-2 colours in P')
 //     (Section 4.3, Algorithm EBBkC-C).
 // Nodes with l = 4 or 5 hand their children (l = 2 or 3) to lanes, one child
-// per lane; everything above is wave-uniform with the lanes owning rows.
+// per lane, after renumbering onto one word fewer when the node's candidate
+// set fits; everything above is wave-uniform with the lanes owning rows.
 #include <type_traits>
 
 #include "arena.h"

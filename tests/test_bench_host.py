@@ -72,3 +72,15 @@ def test_step_plan_keeps_the_wall_budget():
         t += 85.0
         timed += 1
     assert (warm, timed) == (1, 1) and t <= 300.0 + 85.0
+
+
+def test_kernel_hash_ignores_comments_but_not_code():
+    sys.path.insert(0, ROOT)
+    import bench as tp
+    base = {"search.hip": "int f(int a) {\n  return a + 1; // one\n}\n", "build.h": "/* b */ int g;\n",
+            "arena.h": "", "device_util.h": "", "common.h": ""}
+    h0 = tp.source_sha256(base.get)
+    recommented = dict(base, **{"search.hip": "// header\nint f(int a) {   return a + 1; /* one */ }\n"})
+    assert tp.source_sha256(recommented.get) == h0
+    changed = dict(base, **{"search.hip": "int f(int a) {\n  return a + 2; // one\n}\n"})
+    assert tp.source_sha256(changed.get) != h0
