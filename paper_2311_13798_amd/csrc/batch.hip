@@ -136,10 +136,22 @@ __global__ void k_bgather(const int64_t* __restrict__ tasks, const int32_t* __re
     }
 }
 
+// tasks per width class: counted per lane, summed per wave, one atomic per
+// wave and class (one atomic per task on four counters took 17 s for the
+// 1.46e9 tasks of the 4,096-graph batch)
 __global__ void k_bclass_hist(const uint64_t* __restrict__ keys, int64_t n, int gbits,
                               unsigned long long* __restrict__ cls) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        atomicAdd(&cls[(keys[i] >> (8 + gbits)) & 3], 1ull);
+    uint64_t per_class[4] = {0, 0, 0, 0};
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int w = (int)((keys[i] >> (8 + gbits)) & 3);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) per_class[q] += q == w ? 1 : 0;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const uint64_t t = wave_sum(per_class[q]);
+        if (lane_id() == 0 && t) atomicAdd(&cls[q], (unsigned long long)t);
+    }
 }
 
 // zero the counters and per-graph totals (a kernel, so the captured graph

@@ -156,6 +156,7 @@ __global__ void k_task_counts(const int32_t* __restrict__ seed_c, int64_t i0, in
 __global__ void k_task_fill(const int32_t* __restrict__ seed_c, int64_t i0, int64_t n, int l0, double log_thr,
                             const int64_t* __restrict__ toff, int64_t* __restrict__ tasks, uint64_t* __restrict__ keys,
                             uint32_t* __restrict__ vals, unsigned long long* __restrict__ cls_count) {
+    uint64_t per_class[4] = {0, 0, 0, 0};  // tasks per width class, added once per wave below
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         const int c = seed_c[i0 + i];
         if (c < l0) continue;
@@ -169,7 +170,13 @@ __global__ void k_task_fill(const int32_t* __restrict__ seed_c, int64_t i0, int6
             vals[o] = (uint32_t)o;
             ++o;
         });
-        atomicAdd(&cls_count[W - 1], (unsigned long long)nt);
+#pragma unroll
+        for (int w = 0; w < 4; ++w) per_class[w] += w == W - 1 ? (uint64_t)nt : 0;
+    }
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+        const uint64_t t = wave_sum(per_class[w]);
+        if (lane_id() == 0 && t) atomicAdd(&cls_count[w], (unsigned long long)t);
     }
 }
 
