@@ -96,6 +96,43 @@ __device__ __forceinline__ bool later_edge(const GraphView& G, int32_t x, int32_
     return q < G.rp[x + 1] && G.ci[q] == w && G.erank[q] > r;
 }
 
+// later_edge for PB pairs (x[t], w[t]) at once: with the bitmap, every load
+// of the first step (bitmap word, row start, entries before the word) is
+// issued before any is used, then the rank loads of the pairs that are edges,
+// so the PB chains of dependent loads overlap instead of following each other.
+template <int PB>
+__device__ __forceinline__ void later_edges(const GraphView& G, const int32_t (&x)[PB], const int32_t (&w)[PB],
+                                            const bool (&valid)[PB], int32_t r, bool (&ok)[PB]) {
+    if (G.adj) {
+        uint64_t word[PB];
+        int32_t row0[PB], below[PB];
+#pragma unroll
+        for (int t = 0; t < PB; ++t) {
+            word[t] = 0;
+            row0[t] = 0;
+            below[t] = 0;
+            if (valid[t]) {
+                const int64_t o = (int64_t)x[t] * G.adjw + (w[t] >> 6);
+                word[t] = G.adj[o];
+                row0[t] = G.rp[x[t]];
+                below[t] = (int32_t)G.acum[o];
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < PB; ++t) {
+            ok[t] = false;
+            if (valid[t] && ((word[t] >> (w[t] & 63)) & 1))
+                ok[t] = G.erank[row0[t] + below[t] + popc64(word[t] & ((1ull << (w[t] & 63)) - 1))] > r;
+        }
+    } else {
+#pragma unroll
+        for (int t = 0; t < PB; ++t) ok[t] = valid[t] && later_edge(G, x[t], w[t], r);
+    }
+}
+
+// pairs (or row entries) a lane tests per round of the build
+constexpr int BUILD_PB = 4;
+
 // number of entries of row x (rank-sorted, descending) ranked after r
 __device__ __forceinline__ int prefix_after(const int32_t* __restrict__ rp, const int2* __restrict__ rrow, int32_t x,
                                             int32_t r) {
@@ -126,20 +163,27 @@ __device__ int build_subbranch(const GraphView& G, int32_t u, int32_t v, int32_t
     const int32_t xs = lu <= lv ? u : v, ys = lu <= lv ? v : u;
     const int lx = lu <= lv ? lu : lv;
     int c = 0;
-    for (int base = 0; base < lx; base += 64) {
-        const int idx = base + lane;
-        bool ok = false;
-        int32_t w = -1;
-        if (idx < lx) {
-            w = G.rrow[G.rp[xs] + idx].x;
-            ok = later_edge(G, ys, w, r);
+    const int32_t xrow = G.rp[xs];
+    for (int base = 0; base < lx; base += 64 * BUILD_PB) {
+        int32_t wv[BUILD_PB], yv[BUILD_PB];
+        bool val[BUILD_PB], okv[BUILD_PB];
+#pragma unroll
+        for (int t = 0; t < BUILD_PB; ++t) {
+            const int idx = base + 64 * t + lane;
+            val[t] = idx < lx;
+            wv[t] = val[t] ? G.rrow[xrow + idx].x : -1;
+            yv[t] = ys;
         }
-        const uint64_t mk = ballot(ok);
-        if (ok) {
-            const int p = c + popc64(mk & lanemask_lt());
-            if (p < CAP) S.gid[p] = w;
+        later_edges<BUILD_PB>(G, yv, wv, val, r, okv);
+#pragma unroll
+        for (int t = 0; t < BUILD_PB; ++t) {  // in row order, as one entry per lane per round
+            const uint64_t mk = ballot(okv[t]);
+            if (okv[t]) {
+                const int p = c + popc64(mk & lanemask_lt());
+                if (p < CAP) S.gid[p] = wv[t];
+            }
+            c += popc64(mk);
         }
-        c += popc64(mk);
     }
     c = uniform_i32(c);
     if (c > CAP || (expect >= 0 && c != expect)) return -1;
@@ -151,14 +195,26 @@ __device__ int build_subbranch(const GraphView& G, int32_t u, int32_t v, int32_t
     if (G.adj) {
         wave_sync();
         const int U = c * (c - 1) / 2;
-        for (int u0 = 0; u0 < U; u0 += 64) {
-            const int u = u0 + lane;
-            if (u < U) {
-                int i, j;
-                upper_pair(u, c, i, j);
-                if (later_edge(G, S.gid[i], S.gid[j], r)) {
-                    atomicOr((unsigned long long*)&rows[i][j >> 6], 1ull << (j & 63));
-                    atomicOr((unsigned long long*)&rows[j][i >> 6], 1ull << (i & 63));
+        for (int u0 = 0; u0 < U; u0 += 64 * BUILD_PB) {
+            int pi[BUILD_PB], pj[BUILD_PB];
+            int32_t xa[BUILD_PB], wb[BUILD_PB];
+            bool val[BUILD_PB], okv[BUILD_PB];
+#pragma unroll
+            for (int t = 0; t < BUILD_PB; ++t) {
+                const int u = u0 + 64 * t + lane;
+                val[t] = u < U;
+                pi[t] = 0;
+                pj[t] = 0;
+                if (val[t]) upper_pair(u, c, pi[t], pj[t]);
+                xa[t] = val[t] ? S.gid[pi[t]] : 0;
+                wb[t] = val[t] ? S.gid[pj[t]] : 0;
+            }
+            later_edges<BUILD_PB>(G, xa, wb, val, r, okv);
+#pragma unroll
+            for (int t = 0; t < BUILD_PB; ++t) {
+                if (okv[t]) {
+                    atomicOr((unsigned long long*)&rows[pi[t]][pj[t] >> 6], 1ull << (pj[t] & 63));
+                    atomicOr((unsigned long long*)&rows[pj[t]][pi[t] >> 6], 1ull << (pi[t] & 63));
                 }
             }
         }
